@@ -1,0 +1,329 @@
+"""FP64 CPU oracle for the SPH neighbour-interaction sweep.
+
+TEST INFRASTRUCTURE ONLY.  The product library never imports, links or runs
+anything in this package; only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` do.  The oracle shares no code with the GPU
+path: the heavy loops are plain C in ``sph_oracle.c`` (built with gcc,
+``-ffp-contract=off``), and this module only marshals numpy arrays and composes
+the kick-drift-kick sequence.
+
+Passages followed (section numbers of the paper):
+  * kernels .......................... Sec. 2.3 (cubic spline, Wendland C2/C4/C6)
+  * neighbour sets ................... Sec. 2.3.2 (gather / gather+scatter sets)
+  * density, grad-h term, h solve .... Sec. 2.3.3 (eq:Density_estimate, constant kernel mass)
+  * equation of state ................ Sec. 2.3.1
+  * forces, du/dt, viscosity ......... Sec. 2.3.5 (eq:AV_heating)
+  * time-step limits ................. Sec. 2.3.6 (eq:courant_condition, acceleration limit)
+  * kick-drift-kick with predictor ... Sec. 2.3.6 (predictor, closing/opening kicks, drift)
+
+Parity status: every function here is pinned by a ``-m "not gpu"`` test in
+``tests/test_oracle_*.py`` except the energy-drift level over several steps,
+which is "parity unpinned" (the paper quotes only whole-run energy errors).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from ctypes import c_double, c_int, c_int32, c_int64, POINTER
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sph_oracle.c")
+_LIB = os.path.join(_HERE, "libsph_oracle.so")
+
+KERNELS = {"m4": 0, "wc2": 1, "wc4": 2, "wc6": 3}
+EOS = {"ideal": 0, "stiffened": 1}
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no FMA contraction, OpenMP for timing)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = POINTER(c_double)
+        ip = POINTER(c_int64)
+        pp = POINTER(Params)
+        L.orc_sigma.restype = c_double
+        L.orc_sigma.argtypes = [c_int]
+        L.orc_num_threads.restype = c_int
+        L.orc_params_size.restype = c_int
+        L.orc_kernel_shape.argtypes = [c_int, c_int64, dp, dp, dp]
+        L.orc_kernel_w.argtypes = [c_int, c_int64, dp, dp, dp, dp, dp]
+        L.orc_neighbors.argtypes = [pp, c_int64, dp, dp, dp, dp, c_int, ip, ip, ip]
+        L.orc_neighbors.restype = c_int
+        L.orc_density.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, dp, dp, dp, ip]
+        L.orc_density.restype = c_int
+        L.orc_solve_h.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, dp, dp, ip,
+                                  POINTER(c_int32), POINTER(c_int64)]
+        L.orc_solve_h.restype = c_int
+        L.orc_eos.argtypes = [pp, c_int64, dp, dp, dp, dp]
+        L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [dp] * 5 + [ip]
+        L.orc_forces.restype = c_int
+        if L.orc_params_size() != ctypes.sizeof(Params):
+            raise RuntimeError("oracle parameter layout mismatch")
+        _lib = L
+    return _lib
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("kernel", c_int32), ("periodic", c_int32), ("eos", c_int32), ("nr_maxit", c_int32),
+        ("n_ngb", c_double), ("lo", c_double * 3), ("hi", c_double * 3),
+        ("gamma", c_double), ("P0", c_double),
+        ("alpha", c_double), ("beta", c_double), ("eps_av", c_double),
+        ("eta_c", c_double), ("eta_a", c_double), ("dt_max", c_double),
+        ("h_max", c_double), ("nr_tol", c_double),
+    ]
+
+
+def make_params(p: dict) -> Params:
+    """Build the C parameter block from the plain dict used by the input generators."""
+    q = Params()
+    k = p.get("kernel", "m4")
+    q.kernel = KERNELS[k] if isinstance(k, str) else int(k)
+    q.periodic = int(bool(p.get("periodic", True)))
+    e = p.get("eos", "ideal")
+    q.eos = EOS[e] if isinstance(e, str) else int(e)
+    q.nr_maxit = int(p.get("oracle_nr_maxit", 200))
+    q.n_ngb = float(p["n_ngb"])
+    lo = p.get("box_lo", (0.0, 0.0, 0.0))
+    hi = p.get("box_hi", (1.0, 1.0, 1.0))
+    for a in range(3):
+        q.lo[a] = float(lo[a])
+        q.hi[a] = float(hi[a])
+    q.gamma = float(p.get("gamma", 5.0 / 3.0))
+    q.P0 = float(p.get("P0", 0.0))
+    q.alpha = float(p.get("alpha", 1.0))
+    q.beta = float(p.get("beta", 2.0))
+    q.eps_av = float(p.get("eps_av", 0.01))
+    q.eta_c = float(p.get("eta_c", 0.3))
+    q.eta_a = float(p.get("eta_a", 0.2))
+    q.dt_max = float(p.get("dt_max", 1.0))
+    q.h_max = float(p.get("h_max", 0.25))
+    q.nr_tol = float(p.get("oracle_nr_tol", 1e-14))
+    return q
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(POINTER(c_double))
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(POINTER(c_int64))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def sigma(kernel) -> float:
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    return float(lib().orc_sigma(k))
+
+
+def kernel_shape(kernel, q):
+    """f(q) and f'(q) of the normalised shape function (support q < 1)."""
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    q, qp = _d(q)
+    f, fp_ = _d(np.zeros_like(q))
+    d, dp_ = _d(np.zeros_like(q))
+    lib().orc_kernel_shape(k, q.size, qp, fp_, dp_)
+    return f, d
+
+
+def kernel_w(kernel, r, H):
+    """W(r, H), dW/dr and dW/dH (H is the support radius)."""
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    r, rp = _d(r)
+    H, Hp = _d(np.broadcast_to(H, r.shape))
+    outs = [_d(np.zeros_like(r)) for _ in range(3)]
+    lib().orc_kernel_w(k, r.size, rp, Hp, *[o[1] for o in outs])
+    return tuple(o[0] for o in outs)
+
+
+def neighbors(params: dict, x, y, z, H, mode: int = 0):
+    """CSR neighbour sets (rows ascending, self excluded).
+
+    mode 0: gather set  {j != i : r_ij^2 < H_i^2}
+    mode 1: force set   {j != i : r_ij^2 < max(H_i, H_j)^2}
+    """
+    P = make_params(params)
+    n = len(x)
+    arrs = [_d(v) for v in (x, y, z, H)]
+    counts, cp = _i(np.zeros(n, dtype=np.int64))
+    rc = lib().orc_neighbors(ctypes.byref(P), n, *[a[1] for a in arrs], mode, cp, None, None)
+    if rc != 0:
+        raise RuntimeError("oracle neighbour search failed")
+    offsets = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=offsets[1:])
+    offsets, op = _i(offsets)
+    idx, ip = _i(np.zeros(max(int(offsets[-1]), 1), dtype=np.int64))
+    rc = lib().orc_neighbors(ctypes.byref(P), n, *[a[1] for a in arrs], mode, cp, op, ip)
+    if rc != 0:
+        raise RuntimeError("oracle neighbour search failed")
+    return offsets, idx[: int(offsets[-1])]
+
+
+def density(params: dict, x, y, z, m, H):
+    """rho, d rho / dH, Omega and |G_i| at the given support radii."""
+    P = make_params(params)
+    n = len(x)
+    ins = [_d(v) for v in (x, y, z, m, H)]
+    outs = [_d(np.zeros(n)) for _ in range(3)]
+    cnt, cp = _i(np.zeros(n, dtype=np.int64))
+    rc = lib().orc_density(ctypes.byref(P), n, *[a[1] for a in ins], *[o[1] for o in outs], cp)
+    if rc != 0:
+        raise RuntimeError("oracle density failed")
+    return outs[0][0], outs[1][0], outs[2][0], cnt
+
+
+def solve_h(params: dict, x, y, z, m, H0):
+    """Support radii solving (4 pi/3) H^3 rho(H) = n_ngb m_i, with rho, Omega there."""
+    P = make_params(params)
+    n = len(x)
+    ins = [_d(v) for v in (x, y, z, m)]
+    H, Hp = _d(np.array(H0, dtype=np.float64, copy=True))
+    rho, rp = _d(np.zeros(n))
+    om, op = _d(np.zeros(n))
+    cnt, cp = _i(np.zeros(n, dtype=np.int64))
+    its = np.zeros(n, dtype=np.int32)
+    bad = c_int64(0)
+    rc = lib().orc_solve_h(ctypes.byref(P), n, *[a[1] for a in ins], Hp, rp, op, cp,
+                           its.ctypes.data_as(POINTER(c_int32)), ctypes.byref(bad))
+    if rc != 0:
+        raise RuntimeError("oracle smoothing-length solve failed")
+    return {"H": H, "rho": rho, "omega": om, "count": cnt, "iters": its,
+            "n_noconv": int(bad.value)}
+
+
+def eos(params: dict, rho, u):
+    P = make_params(params)
+    rho, rp = _d(rho)
+    u, up = _d(u)
+    Pr, Pp = _d(np.zeros_like(rho))
+    c, cp = _d(np.zeros_like(rho))
+    lib().orc_eos(ctypes.byref(P), rho.size, rp, up, Pp, cp)
+    return Pr, c
+
+
+def forces(params: dict, x, y, z, vx, vy, vz, m, H, rho, omega, P, c):
+    """Accelerations, du/dt, per-particle time-step limit and |F_i|."""
+    Pp = make_params(params)
+    n = len(x)
+    ins = [_d(v) for v in (x, y, z, vx, vy, vz, m, H, rho, omega, P, c)]
+    outs = [_d(np.zeros(n)) for _ in range(5)]
+    cnt, cp = _i(np.zeros(n, dtype=np.int64))
+    rc = lib().orc_forces(ctypes.byref(Pp), n, *[a[1] for a in ins], *[o[1] for o in outs], cp)
+    if rc != 0:
+        raise RuntimeError("oracle forces failed")
+    ax, ay, az, dudt, dti = (o[0] for o in outs)
+    return {"ax": ax, "ay": ay, "az": az, "dudt": dudt, "dt": dti, "count": cnt}
+
+
+# ---------------------------------------------------------------------------
+# Time integration (Sec. 2.3.6), global time step.  State arrays are FP64.
+# Start-up (not spelt out in the paper): density and forces at t0.  One step:
+#   1. opening kick   v_half = v + (dt/2) a,   u_half = u + (dt/2) du
+#   2. drift          x = x + dt v_half, wrapped into the periodic box
+#   3. density pass at the new positions (H from the previous step as guess)
+#   4. predictor      v_p = v_half + (dt/2) a_old,  u_p likewise
+#   5. EOS at (rho, u_p), forces with (v_p, u_p)
+#   6. closing kick   v = v_half + (dt/2) a_new,   u likewise
+# which is the paper's density / predict / force+closing kick / opening kick
+# / drift loop regrouped so that a step ends with synchronised v and u.
+# ---------------------------------------------------------------------------
+
+STATE_KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H")
+
+
+def init(params: dict, state: dict) -> dict:
+    """Density and forces at the initial time; fills rho, omega, P, c, a, dudt, dt."""
+    s = {k: np.array(state[k], dtype=np.float64, copy=True) for k in STATE_KEYS}
+    d = solve_h(params, s["x"], s["y"], s["z"], s["m"], s["H"])
+    s["H"], s["rho"], s["omega"] = d["H"], d["rho"], d["omega"]
+    s["n_noconv"] = d["n_noconv"]
+    s["P"], s["c"] = eos(params, s["rho"], s["u"])
+    f = forces(params, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], s["H"],
+               s["rho"], s["omega"], s["P"], s["c"])
+    for k in ("ax", "ay", "az", "dudt", "dt"):
+        s[k] = f[k]
+    s["n_d"] = int(d["count"].sum())
+    s["n_f"] = int(f["count"].sum())
+    return s
+
+
+def global_dt(params: dict, s: dict) -> float:
+    return float(min(np.min(s["dt"]) if len(s["dt"]) else np.inf, params.get("dt_max", 1.0)))
+
+
+def _wrap(params: dict, v, a):
+    if not params.get("periodic", True):
+        return v
+    lo = float(params.get("box_lo", (0.0, 0.0, 0.0))[a])
+    hi = float(params.get("box_hi", (1.0, 1.0, 1.0))[a])
+    L = hi - lo
+    return v - L * np.floor((v - lo) / L)
+
+
+def step(params: dict, s: dict, dt: float | None = None) -> dict:
+    """One kick-drift-kick step in place; returns the FP64 report."""
+    if dt is None or dt <= 0:
+        dt = global_dt(params, s)
+    hdt = 0.5 * dt
+    vxh = s["vx"] + hdt * s["ax"]
+    vyh = s["vy"] + hdt * s["ay"]
+    vzh = s["vz"] + hdt * s["az"]
+    uh = s["u"] + hdt * s["dudt"]
+    s["x"] = _wrap(params, s["x"] + dt * vxh, 0)
+    s["y"] = _wrap(params, s["y"] + dt * vyh, 1)
+    s["z"] = _wrap(params, s["z"] + dt * vzh, 2)
+    d = solve_h(params, s["x"], s["y"], s["z"], s["m"], s["H"])
+    s["H"], s["rho"], s["omega"] = d["H"], d["rho"], d["omega"]
+    vxp = vxh + hdt * s["ax"]
+    vyp = vyh + hdt * s["ay"]
+    vzp = vzh + hdt * s["az"]
+    up = uh + hdt * s["dudt"]
+    s["P"], s["c"] = eos(params, s["rho"], up)
+    f = forces(params, s["x"], s["y"], s["z"], vxp, vyp, vzp, s["m"], s["H"],
+               s["rho"], s["omega"], s["P"], s["c"])
+    for k in ("ax", "ay", "az", "dudt", "dt"):
+        s[k] = f[k]
+    s["vx"] = vxh + hdt * s["ax"]
+    s["vy"] = vyh + hdt * s["ay"]
+    s["vz"] = vzh + hdt * s["az"]
+    s["u"] = uh + hdt * s["dudt"]
+    s["n_noconv"] = d["n_noconv"]
+    s["n_d"] = int(d["count"].sum())
+    s["n_f"] = int(f["count"].sum())
+    rep = reductions(s)
+    rep["dt"] = dt
+    return rep
+
+
+def reductions(s: dict) -> dict:
+    """Total momentum, kinetic and internal energy (FP64 sums)."""
+    m = s["m"]
+    px = float(np.sum(m * s["vx"]))
+    py = float(np.sum(m * s["vy"]))
+    pz = float(np.sum(m * s["vz"]))
+    ek = float(np.sum(0.5 * m * (s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)))
+    ei = float(np.sum(m * s["u"]))
+    return {"momentum": (px, py, pz), "e_kin": ek, "e_int": ei, "e_tot": ek + ei}
