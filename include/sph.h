@@ -1,0 +1,206 @@
+/*
+ * sph.h -- C interface of the MI355X (gfx950) SPH neighbour-interaction sweep.
+ *
+ * The sweep is the per-step hot path of the tree-SPH method of "Smoothed
+ * Particle Hydrodynamics in pkdgrav3 for Shock Physics Simulations. I.
+ * Hydrodynamics" (Meier, Potter, Reinhardt, Stadel):
+ *   tree build over particle buckets          (Sec. 2.1 reordered storage, Sec. 2.3.2 bounds)
+ *   bucket neighbour search by bound overlap  (Sec. 2.3.2, Fig. 1)
+ *   density sum + smoothing-length iteration (Sec. 2.3.3, eq:Density_estimate)
+ *   force loop, du/dt, viscosity, time step  (Sec. 2.3.5, eq:AV_heating; Sec. 2.3.6, eq:courant_condition)
+ *   kick-drift-kick with predictor            (Sec. 2.3.6)
+ *
+ * Conventions
+ *   H        kernel support radius (W = 0 for r >= H); h = H/2 is the smoothing
+ *            length that enters the viscosity and the Courant limit.
+ *   x_ij     x_i - x_j, minimum image per component in a periodic box.
+ *   G_i      gather set {j != i : r_ij^2 < H_i^2}; the density includes i.
+ *   F_i      force set  {j != i : r_ij^2 < max(H_i, H_j)^2}.
+ *
+ * Memory and ownership
+ *   Every particle array in sph_particles is a caller-owned DEVICE pointer to
+ *   n contiguous doubles in the caller's particle order (structure of arrays).
+ *   The caller keeps them alive until the work enqueued on the stream has
+ *   completed.  The context owns everything else (sorted copies, tree,
+ *   counters) and reuses it: after the first call at a given n no further
+ *   device allocation happens, so the step can be captured into a HIP graph.
+ *   A context is not thread-safe; use one context per stream.
+ *
+ * Streams
+ *   `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *   work is enqueued asynchronously; no call synchronises the host except
+ *   sph_neighbors (it returns the needed size), sph_get_stats and
+ *   sph_autotune.
+ *
+ * Errors
+ *   Argument errors return SPH_ERR_INVALID synchronously and enqueue nothing.
+ *   HIP runtime errors return SPH_ERR_HIP.  Conditions found on the device
+ *   (smoothing-length cap reached, a walk stack overflow) are counted in
+ *   device counters and reported by sph_get_stats.  sph_last_error() gives a
+ *   text for the last failing call.  No C++ exception crosses this interface.
+ */
+#ifndef SPH_MI355X_H
+#define SPH_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx;
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_ERR_INVALID = 1,  /* bad argument, shape or parameter */
+    SPH_ERR_OOM = 2,      /* device allocation failed */
+    SPH_ERR_HIP = 3,      /* HIP runtime error */
+    SPH_ERR_CAPACITY = 4, /* output buffer too small (see sph_neighbors) */
+    SPH_ERR_NOCONV = 5,   /* reserved: reported through sph_stats.n_noconv */
+    SPH_ERR_STATE = 6     /* call out of order (e.g. density before a tree) */
+} sph_status;
+
+enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WC2 = 1, SPH_KERNEL_WC4 = 2, SPH_KERNEL_WC6 = 3 };
+enum { SPH_PREC_FP64 = 0, SPH_PREC_MIXED = 1 };
+enum { SPH_EOS_IDEAL = 0, SPH_EOS_STIFFENED = 1 };
+enum { SPH_MODE_GATHER = 0, SPH_MODE_FORCE = 1 };
+
+/* Method parameters.  sph_default_params() fills the defaults noted here. */
+typedef struct {
+    int32_t kernel;    /* SPH_KERNEL_*: cubic spline (Monaghan 1992) or Wendland C2/C4/C6
+                          (Dehnen & Aly 2012), Sec. 2.3.  Default M4. */
+    int32_t precision; /* SPH_PREC_FP64: all pair arithmetic in FP64.
+                          SPH_PREC_MIXED: pair arithmetic in FP32 on bucket-relative
+                          coordinates with compensated sums; positions, the step and
+                          the global reductions stay FP64.  Default FP64. */
+    int32_t eos;       /* SPH_EOS_IDEAL: P = (gamma-1) rho u (Sec. 2.3.1).
+                          SPH_EOS_STIFFENED: P = (gamma-1) rho u - gamma P0. */
+    int32_t periodic;  /* 1: periodic box [box_lo, box_hi) with minimum image;
+                          0: open boundary (box ignored).  Default 1. */
+    double n_ngb;      /* target neighbour number of the constant kernel mass rule
+                          (4 pi/3) H^3 rho = n_ngb m_i (Sec. 2.3.3).  Must exceed
+                          (4 pi/3) sigma of the kernel.  Default 64. */
+    double box_lo[3], box_hi[3]; /* periodic box.  Default unit cube. */
+    double gamma, P0;  /* EOS constants.  Default 5/3, 0. */
+    double alpha, beta, eps_av; /* Monaghan viscosity (Sec. 2.3.5).  Default 1, 2, 0.01. */
+    double eta_c, eta_a, dt_max; /* Courant factor, acceleration factor (Sec. 2.3.6),
+                                    cap on the step.  Default 0.3, 0.2, 1. */
+    double h_max;      /* cap on H (also kept below half the periodic box).  Default 0.25. */
+    double oversel;    /* the density pass searches with oversel*H so the iteration can
+                          grow H without a new walk (Sec. 2.3.3).  Default 1.1. */
+    double nr_tol;     /* relative tolerance on H.  Default 1e-14 (FP64), 1e-6 (mixed)
+                          when left at 0. */
+    int32_t nr_maxit;  /* iteration cap.  Default 64. */
+    int32_t bucket;    /* particles per bucket: 16, 32 or 64; 0 = autotuned.  Default 32. */
+} sph_params;
+
+/* Caller-owned device arrays, n doubles each, caller particle order.
+ * State: x y z (positions inside the periodic box), vx vy vz, m, u, H.
+ * Results written by the calls: rho, omega (grad-h term), P, c (pressure and
+ * sound speed), ax ay az, dudt, dt (per-particle time-step limit). */
+typedef struct {
+    double *x, *y, *z, *vx, *vy, *vz, *m, *u, *H;
+    double *rho, *omega, *P, *c, *ax, *ay, *az, *dudt, *dt;
+} sph_particles;
+
+/* Counters of the most recent call, read with sph_get_stats. */
+typedef struct {
+    int64_t n;                    /* particles */
+    int64_t pairs_density;        /* sum_i |G_i| at the converged H */
+    int64_t pairs_force;          /* sum_i |F_i| */
+    int64_t cand_density;         /* candidate particles tested, summed over sinks and scans */
+    int64_t cand_force;           /* candidate particles tested in the force pass */
+    int64_t nr_iter_max;          /* largest number of density scans in a sink group */
+    int64_t nr_scans;             /* density scans summed over sink groups */
+    int64_t n_noconv;             /* particles whose H hit the cap or the iteration limit */
+    int64_t n_rewalk;             /* sink groups re-walked because H outgrew the search radius */
+    int64_t n_overflow;           /* walk stack overflows (results invalid if nonzero) */
+    double momentum[3];           /* sum m v after the last step (FP64) */
+    double e_kin, e_int;          /* sum m v^2/2, sum m u after the last step (FP64) */
+    double dt_next;               /* min_i dt_i from the last force pass, capped by dt_max */
+    double dt_used;               /* step size of the last sph_step */
+} sph_stats;
+
+/* Fills *p with the defaults listed above. */
+void sph_default_params(sph_params *p);
+
+/* Library version text (static storage). */
+const char *sph_version(void);
+
+/* Text of the last error on this context (static storage owned by ctx). */
+const char *sph_last_error(const sph_ctx *ctx);
+
+/* Creates a context for one particle set.  Allocates nothing on the device
+ * until the first sph_build_tree.  Returns SPH_ERR_INVALID on bad params. */
+sph_status sph_create(const sph_params *params, sph_ctx **out);
+
+/* Creates a context for `nsets` independent particle sets processed together
+ * (one tree per set, all sets in the same launches).  set_offsets: host array
+ * of nsets+1 increasing int64; set s owns particles [set_offsets[s],
+ * set_offsets[s+1]) of every particle array.  set_box: host array of
+ * 6*nsets doubles (lo x y z, hi x y z per set) or NULL for params->box_*.
+ * nsets <= 4096. */
+sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64_t *set_offsets,
+                            const double *set_box, sph_ctx **out);
+
+/* Frees the context and all device memory it owns (synchronises the device). */
+void sph_destroy(sph_ctx *ctx);
+
+/* Tree build (Sec. 2.1, Sec. 2.3.2): Morton keys of x y z within the box,
+ * stable radix sort, gather into sorted order, buckets of `bucket` particles,
+ * cell bounds, box-of-balls and ball-of-balls from H, combined bottom-up over
+ * a binary tree of buckets.  Reads x y z m H.  n must equal the set total for
+ * batch contexts. */
+sph_status sph_build_tree(sph_ctx *ctx, const sph_particles *p, int64_t n, void *stream);
+
+/* Neighbour sets of the current tree and H (Sec. 2.3.2).  mode SPH_MODE_GATHER
+ * gives G_i, SPH_MODE_FORCE gives F_i.  Output in CSR form on the device:
+ * offsets (n+1 int64, row of caller particle i = [offsets[i], offsets[i+1]))
+ * and idx (int32 caller indices; in a batch context, indices into the whole
+ * concatenated particle arrays), each row ascending, self excluded.  If capacity < total the call writes offsets only, sets
+ * *needed (host) and returns SPH_ERR_CAPACITY; call again with a larger idx.
+ * Synchronises the stream.  Rows longer than 4096 return SPH_ERR_CAPACITY. */
+sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int64_t *offsets,
+                         int32_t *idx, int64_t capacity, int64_t *needed, void *stream);
+
+/* Density pass (Sec. 2.3.3) on the current tree: per particle, H solving
+ * (4 pi/3) H^3 rho(H) = n_ngb m_i by safeguarded Newton iteration on the
+ * over-selected candidate list, rho = sum_{G_i + i} m_j W(r_ij, H_i), and
+ * Omega = 1 + (H/(3 rho)) d rho/dH.  Reads H as the first guess; writes H,
+ * rho, omega; refits the ball bounds of the tree with the new H. */
+sph_status sph_density(sph_ctx *ctx, sph_particles *p, void *stream);
+
+/* Force pass (Sec. 2.3.5, 2.3.6) on the current tree and H: EOS from rho and
+ * u (written to P, c), then a, du/dt (pressure + viscosity) and the
+ * per-particle limit dt = min(eta_a sqrt(H/|a|), Courant limit, dt_max).
+ * Uses v and u as given. */
+sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream);
+
+/* Start-up: sph_build_tree(n) + density + forces at the initial time, and the
+ * reductions (so sph_step can take its first dt from the device). */
+sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream);
+
+/* One kick-drift-kick step (Sec. 2.3.6) with global step dt (dt <= 0: the
+ * minimum per-particle limit of the previous force pass, read on the device):
+ * opening kick, drift with periodic wrap, tree build, density, predictor,
+ * EOS, forces with the predicted v and u, closing kick, FP64 reductions.
+ * Requires a previous sph_init or sph_step. */
+sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream);
+
+/* Captures one sph_step (same arguments) into a HIP graph owned by the
+ * context and launches nothing.  sph_graph_launch replays it on `stream`. */
+sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream);
+sph_status sph_graph_launch(sph_ctx *ctx, void *stream);
+
+/* Picks the bucket size by timing the density and force passes on the given
+ * particles (synchronises; leaves H, rho, omega, P, c, a, dudt, dt written as
+ * by sph_init).  The choice is kept in the context; returns it in *bucket. */
+sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *stream);
+
+/* Synchronises the context's last stream and copies the counters. */
+sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_MI355X_H */

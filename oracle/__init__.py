@@ -67,13 +67,13 @@ def lib():
         L.orc_kernel_w.argtypes = [c_int, c_int64, dp, dp, dp, dp, dp]
         L.orc_neighbors.argtypes = [pp, c_int64, dp, dp, dp, dp, c_int, ip, ip, ip]
         L.orc_neighbors.restype = c_int
-        L.orc_density.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, dp, dp, dp, ip]
+        L.orc_density.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, ip, c_int64, dp, dp, dp, ip]
         L.orc_density.restype = c_int
-        L.orc_solve_h.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, dp, dp, ip,
+        L.orc_solve_h.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, ip, c_int64, dp, dp, dp, ip,
                                   POINTER(c_int32), POINTER(c_int64)]
         L.orc_solve_h.restype = c_int
         L.orc_eos.argtypes = [pp, c_int64, dp, dp, dp, dp]
-        L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [dp] * 5 + [ip]
+        L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [ip, c_int64] + [dp] * 5 + [ip]
         L.orc_forces.restype = c_int
         if L.orc_params_size() != ctypes.sizeof(Params):
             raise RuntimeError("oracle parameter layout mismatch")
@@ -182,31 +182,43 @@ def neighbors(params: dict, x, y, z, H, mode: int = 0):
     return offsets, idx[: int(offsets[-1])]
 
 
-def density(params: dict, x, y, z, m, H):
-    """rho, d rho / dH, Omega and |G_i| at the given support radii."""
+def _rows(rows, n):
+    if rows is None:
+        return None, None, n
+    r, rp = _i(rows)
+    return r, rp, r.size
+
+
+def density(params: dict, x, y, z, m, H, rows=None):
+    """rho, d rho / dH, Omega and |G_i| at the given support radii (optionally
+    only for the particles listed in ``rows``)."""
     P = make_params(params)
     n = len(x)
     ins = [_d(v) for v in (x, y, z, m, H)]
-    outs = [_d(np.zeros(n)) for _ in range(3)]
-    cnt, cp = _i(np.zeros(n, dtype=np.int64))
-    rc = lib().orc_density(ctypes.byref(P), n, *[a[1] for a in ins], *[o[1] for o in outs], cp)
+    rr, rp, nw = _rows(rows, n)
+    outs = [_d(np.zeros(nw)) for _ in range(3)]
+    cnt, cp = _i(np.zeros(nw, dtype=np.int64))
+    rc = lib().orc_density(ctypes.byref(P), n, *[a[1] for a in ins], rp, nw,
+                           *[o[1] for o in outs], cp)
     if rc != 0:
         raise RuntimeError("oracle density failed")
     return outs[0][0], outs[1][0], outs[2][0], cnt
 
 
-def solve_h(params: dict, x, y, z, m, H0):
-    """Support radii solving (4 pi/3) H^3 rho(H) = n_ngb m_i, with rho, Omega there."""
+def solve_h(params: dict, x, y, z, m, H0, rows=None):
+    """Support radii solving (4 pi/3) H^3 rho(H) = n_ngb m_i, with rho, Omega there
+    (optionally only for the particles listed in ``rows``)."""
     P = make_params(params)
     n = len(x)
-    ins = [_d(v) for v in (x, y, z, m)]
-    H, Hp = _d(np.array(H0, dtype=np.float64, copy=True))
-    rho, rp = _d(np.zeros(n))
-    om, op = _d(np.zeros(n))
-    cnt, cp = _i(np.zeros(n, dtype=np.int64))
-    its = np.zeros(n, dtype=np.int32)
+    ins = [_d(v) for v in (x, y, z, m, H0)]
+    rr, rowp, nw = _rows(rows, n)
+    H, Hp = _d(np.zeros(nw))
+    rho, rp = _d(np.zeros(nw))
+    om, op = _d(np.zeros(nw))
+    cnt, cp = _i(np.zeros(nw, dtype=np.int64))
+    its = np.zeros(nw, dtype=np.int32)
     bad = c_int64(0)
-    rc = lib().orc_solve_h(ctypes.byref(P), n, *[a[1] for a in ins], Hp, rp, op, cp,
+    rc = lib().orc_solve_h(ctypes.byref(P), n, *[a[1] for a in ins], rowp, nw, Hp, rp, op, cp,
                            its.ctypes.data_as(POINTER(c_int32)), ctypes.byref(bad))
     if rc != 0:
         raise RuntimeError("oracle smoothing-length solve failed")
@@ -224,14 +236,17 @@ def eos(params: dict, rho, u):
     return Pr, c
 
 
-def forces(params: dict, x, y, z, vx, vy, vz, m, H, rho, omega, P, c):
-    """Accelerations, du/dt, per-particle time-step limit and |F_i|."""
+def forces(params: dict, x, y, z, vx, vy, vz, m, H, rho, omega, P, c, rows=None):
+    """Accelerations, du/dt, per-particle time-step limit and |F_i| (optionally
+    only for the particles listed in ``rows``)."""
     Pp = make_params(params)
     n = len(x)
     ins = [_d(v) for v in (x, y, z, vx, vy, vz, m, H, rho, omega, P, c)]
-    outs = [_d(np.zeros(n)) for _ in range(5)]
-    cnt, cp = _i(np.zeros(n, dtype=np.int64))
-    rc = lib().orc_forces(ctypes.byref(Pp), n, *[a[1] for a in ins], *[o[1] for o in outs], cp)
+    rr, rowp, nw = _rows(rows, n)
+    outs = [_d(np.zeros(nw)) for _ in range(5)]
+    cnt, cp = _i(np.zeros(nw, dtype=np.int64))
+    rc = lib().orc_forces(ctypes.byref(Pp), n, *[a[1] for a in ins], rowp, nw,
+                          *[o[1] for o in outs], cp)
     if rc != 0:
         raise RuntimeError("oracle forces failed")
     ax, ay, az, dudt, dti = (o[0] for o in outs)

@@ -400,9 +400,11 @@ static dens_val dens_sum(int kernel, double sig, double mi, double H,
     return v;
 }
 
+/* Rows: which == NULL computes every particle (outputs indexed by particle);
+ * otherwise only particles which[0..nw) (outputs indexed 0..nw). */
 int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
-                const double *z, const double *m, const double *H, double *rho,
-                double *drho, double *omega, int64_t *count) {
+                const double *z, const double *m, const double *H, const int64_t *which,
+                int64_t nw, double *rho, double *drho, double *omega, int64_t *count) {
     double L[3], hL[3];
     box_lengths(p, L, hL);
     double sig = orc_sigma(p->kernel);
@@ -413,8 +415,10 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
         plist l = {0};
         double *mj = NULL, *rj = NULL;
         int64_t cap = 0;
+        if (!which) nw = n;
         #pragma omp for schedule(dynamic, 64)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = 0; k < nw; ++k) {
+            int64_t i = which ? which[k] : k;
             grid_query(&g, p, L, hL, x, y, z, i, H[i], &l);
             if (l.n > cap) {
                 cap = l.n;
@@ -423,10 +427,10 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
             }
             for (int64_t t = 0; t < l.n; ++t) { mj[t] = m[l.j[t]]; rj[t] = sqrt(l.r2[t]); }
             dens_val v = dens_sum(p->kernel, sig, m[i], H[i], l.n, mj, l.r2, rj);
-            rho[i] = v.rho;
-            drho[i] = v.drho;
-            omega[i] = 1.0 + H[i] * v.drho / (3.0 * v.rho);
-            count[i] = v.count;
+            rho[k] = v.rho;
+            drho[k] = v.drho;
+            omega[k] = 1.0 + H[i] * v.drho / (3.0 * v.rho);
+            count[k] = v.count;
         }
         free(l.j); free(l.r2); free(mj); free(rj);
     }
@@ -444,9 +448,12 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
 /* box when periodic); a capped particle is counted as not converged.       */
 /* ------------------------------------------------------------------------ */
 
+/* H holds the first guesses of every particle on entry; on return H[i] (or
+ * H[k] for a row subset, see orc_density) holds the solution. */
 int orc_solve_h(const orc_params *p, int64_t n, const double *x, const double *y,
-                const double *z, const double *m, double *H, double *rho,
-                double *omega, int64_t *count, int32_t *iters, int64_t *n_noconv) {
+                const double *z, const double *m, const double *H0, const int64_t *which,
+                int64_t nw, double *H, double *rho, double *omega, int64_t *count,
+                int32_t *iters, int64_t *n_noconv) {
     double L[3], hL[3];
     box_lengths(p, L, hL);
     double sig = orc_sigma(p->kernel);
@@ -460,7 +467,7 @@ int orc_solve_h(const orc_params *p, int64_t n, const double *x, const double *y
     int maxit = p->nr_maxit > 0 ? p->nr_maxit : 200;
     double c43 = 4.0 * ORC_PI / 3.0;
     grid g;
-    double Hm = max_of(n, H);
+    double Hm = max_of(n, H0);
     if (Hm > cap) Hm = cap;
     if (grid_build(&g, p, n, x, y, z, Hm) != 0) return -1;
     int64_t bad = 0;
@@ -469,14 +476,16 @@ int orc_solve_h(const orc_params *p, int64_t n, const double *x, const double *y
         plist l = {0};
         double *mj = NULL, *rj = NULL;
         int64_t lcap = 0;
+        if (!which) nw = n;
         #pragma omp for schedule(dynamic, 16)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = 0; k < nw; ++k) {
+            int64_t i = which ? which[k] : k;
             double target = p->n_ngb * m[i];
-            double H0 = H[i];
-            if (!(H0 > 0)) H0 = cap * 0.01;
-            if (H0 > cap) H0 = cap;
+            double Hg = H0[i];
+            if (!(Hg > 0)) Hg = cap * 0.01;
+            if (Hg > cap) Hg = cap;
             /* Bracket: F(0+) < 0; grow hi until F(hi) >= 0 or the cap. */
-            double hi = H0;
+            double hi = Hg;
             int capped = 0;
             dens_val v;
             for (;;) {
@@ -500,7 +509,7 @@ int orc_solve_h(const orc_params *p, int64_t n, const double *x, const double *y
                 bad++;
             } else {
                 double lo = 0.0;
-                double h = H0 < hi ? H0 : hi;
+                double h = Hg < hi ? Hg : hi;
                 for (it = 1; it <= maxit; ++it) {
                     v = dens_sum(p->kernel, sig, m[i], h, l.n, mj, l.r2, rj);
                     double F = c43 * h * h * h * v.rho - target;
@@ -516,11 +525,11 @@ int orc_solve_h(const orc_params *p, int64_t n, const double *x, const double *y
                 if (it > maxit) bad++;
             }
             v = dens_sum(p->kernel, sig, m[i], Hc, l.n, mj, l.r2, rj);
-            H[i] = Hc;
-            rho[i] = v.rho;
-            omega[i] = 1.0 + Hc * v.drho / (3.0 * v.rho);
-            count[i] = v.count;
-            iters[i] = it;
+            H[k] = Hc;
+            rho[k] = v.rho;
+            omega[k] = 1.0 + Hc * v.drho / (3.0 * v.rho);
+            count[k] = v.count;
+            iters[k] = it;
         }
         free(l.j); free(l.r2); free(mj); free(rj);
     }
@@ -571,8 +580,8 @@ void orc_eos(const orc_params *p, int64_t n, const double *rho, const double *u,
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                const double *z, const double *vx, const double *vy, const double *vz,
                const double *m, const double *H, const double *rho, const double *omega,
-               const double *P, const double *c, double *ax, double *ay, double *az,
-               double *dudt, double *dti, int64_t *count) {
+               const double *P, const double *c, const int64_t *which, int64_t nw,
+               double *ax, double *ay, double *az, double *dudt, double *dti, int64_t *count) {
     double L[3], hL[3];
     box_lengths(p, L, hL);
     double sig = orc_sigma(p->kernel);
@@ -584,8 +593,10 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
     #pragma omp parallel
     {
         plist l = {0};
+        if (!which) nw = n;
         #pragma omp for schedule(dynamic, 64)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = 0; k < nw; ++k) {
+            int64_t i = which ? which[k] : k;
             grid_query(&g, p, L, hL, x, y, z, i, Hmax, &l);
             double Hi2 = H[i] * H[i];
             double hi_s = 0.5 * H[i];
@@ -632,9 +643,9 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                 sav += m[j] * Pi * Gbar * vdotx;
                 if (-mu > mumax) mumax = -mu;
             }
-            ax[i] = sax; ay[i] = say; az[i] = saz;
-            dudt[i] = A[i] * spdv + 0.5 * sav;
-            count[i] = cnt;
+            ax[k] = sax; ay[k] = say; az[k] = saz;
+            dudt[k] = A[i] * spdv + 0.5 * sav;
+            count[k] = cnt;
             double amag = sqrt(sax * sax + say * say + saz * saz);
             double dt = p->dt_max;
             if (amag > 0.0) {
@@ -646,7 +657,7 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                 double tc = p->eta_c * hi_s / den;
                 if (tc < dt) dt = tc;
             }
-            dti[i] = dt;
+            dti[k] = dt;
         }
         free(l.j); free(l.r2);
     }

@@ -1,0 +1,535 @@
+// sph_api.hip -- the C interface (include/sph.h): context, device memory,
+// call sequencing, counters, graph capture and the bucket-size autotuner.
+#include "sph_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+using namespace sphmi;
+
+struct sph_ctx {
+    Ctx c;
+};
+
+namespace {
+
+const char kVersion[] = "sph-mi355x 0.1 (gfx950)";
+
+sph_status fail(sph_ctx *x, sph_status st, const char *msg) {
+    if (x) x->c.err = msg;
+    return st;
+}
+
+sph_status hip_fail(sph_ctx *x, hipError_t e, const char *where) {
+    if (x) {
+        x->c.err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return SPH_ERR_HIP;
+}
+
+#define HIPCHK(x, expr, where)                                  \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return hip_fail((x), e_, where);  \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(Ctx &c, T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * (count > 0 ? count : 1));
+    if (e != hipSuccess) return e;
+    c.allocs.push_back(q);
+    *p = reinterpret_cast<T *>(q);
+    return hipSuccess;
+}
+
+void free_all(Ctx &c) {
+    if (c.graph_exec) { (void)hipGraphExecDestroy(c.graph_exec); c.graph_exec = nullptr; }
+    if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
+    for (void *q : c.allocs) (void)hipFree(q);
+    c.allocs.clear();
+    if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
+    if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
+    c.n = 0;
+    c.have_tree = false;
+    c.have_forces = false;
+}
+
+bool valid_params(const sph_params *p, std::string &why) {
+    if (!p) { why = "params is NULL"; return false; }
+    if (p->kernel < 0 || p->kernel > 3) { why = "kernel must be 0..3"; return false; }
+    if (p->precision != SPH_PREC_FP64 && p->precision != SPH_PREC_MIXED) {
+        why = "precision must be SPH_PREC_FP64 or SPH_PREC_MIXED"; return false;
+    }
+    if (p->eos != SPH_EOS_IDEAL && p->eos != SPH_EOS_STIFFENED) { why = "bad eos"; return false; }
+    static const double sig43[4] = {32.0 / 3.0, 14.0, 165.0 / 8.0, 455.0 / 16.0};
+    if (!(p->n_ngb > sig43[p->kernel])) { why = "n_ngb must exceed (4 pi/3) sigma of the kernel"; return false; }
+    if (p->periodic) {
+        for (int a = 0; a < 3; ++a)
+            if (!(p->box_hi[a] > p->box_lo[a])) { why = "empty periodic box"; return false; }
+    }
+    if (!(p->h_max > 0)) { why = "h_max must be positive"; return false; }
+    if (!(p->oversel >= 1.0)) { why = "oversel must be >= 1"; return false; }
+    if (!(p->gamma > 1.0)) { why = "gamma must exceed 1"; return false; }
+    if (p->nr_maxit < 1) { why = "nr_maxit must be >= 1"; return false; }
+    if (p->bucket != 0 && p->bucket != 16 && p->bucket != 32 && p->bucket != 64) {
+        why = "bucket must be 0, 16, 32 or 64"; return false;
+    }
+    return true;
+}
+
+// Topology of buckets, groups and tree nodes for the current n and bucket size.
+sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
+    Ctx &c = x->c;
+    if (c.n == n && c.allocs.size() > 0) return SPH_OK;
+    free_all(c);
+    const int B = c.bucket;
+    const int ns = c.nsets;
+    std::vector<SetGeom> sets(ns);
+    std::vector<int32_t> grp_set, bkt_set;
+    int64_t b0 = 0, g0 = 0, node0 = 0;
+    int max_depth = 0;
+    for (int q = 0; q < ns; ++q) {
+        SetGeom &g = sets[q];
+        g.p0 = c.set_off[q];
+        g.p1 = c.set_off[q + 1];
+        int64_t np = g.p1 - g.p0;
+        int64_t nb = (np + B - 1) / B;
+        int64_t nbp = 1;
+        int depth = 0;
+        while (nbp < nb) { nbp <<= 1; ++depth; }
+        if (nbp > (int64_t)1 << 30) return fail(x, SPH_ERR_INVALID, "set too large");
+        g.nb = (int32_t)nb;
+        g.nbp = (int32_t)nbp;
+        g.depth = depth;
+        g.b0 = b0;
+        g.g0 = g0;
+        g.node0 = node0;
+        const double *lo = c.set_box.empty() ? c.prm.box_lo : &c.set_box[6 * q];
+        const double *hi = c.set_box.empty() ? c.prm.box_hi : &c.set_box[6 * q + 3];
+        for (int a = 0; a < 3; ++a) {
+            g.lo[a] = lo[a];
+            g.L[a] = hi[a] - lo[a];
+            g.halfL[a] = 0.5 * g.L[a];
+        }
+        int64_t ng = (np + kGroup - 1) / kGroup;
+        for (int64_t k = 0; k < ng; ++k) grp_set.push_back(q);
+        for (int64_t k = 0; k < nb; ++k) bkt_set.push_back(q);
+        b0 += nb;
+        g0 += ng;
+        node0 += 2 * nbp;
+        max_depth = std::max(max_depth, depth);
+    }
+    c.nbuckets = b0;
+    c.ngroups = g0;
+    c.nnodes = node0;
+    c.max_depth = max_depth;
+    // nodes per height d: nbp >> d for sets with depth >= d
+    std::vector<int64_t> pref((size_t)(max_depth + 1) * (ns + 1), 0);
+    c.level_total.assign(max_depth + 1, 0);
+    for (int d = 0; d <= max_depth; ++d) {
+        int64_t acc = 0;
+        for (int q = 0; q < ns; ++q) {
+            pref[(size_t)d * (ns + 1) + q] = acc;
+            if (sets[q].depth >= d && sets[q].nb > 0) acc += (int64_t)(sets[q].nbp >> d);
+        }
+        pref[(size_t)d * (ns + 1) + ns] = acc;
+        c.level_total[d] = acc;
+    }
+    c.set_bits = 0;
+    while ((1 << c.set_bits) < ns) ++c.set_bits;
+    int key_bits = 3 * morton_bits() + c.set_bits;
+    c.key_passes = (key_bits + 7) / 8;
+    c.sort_blocks = sort_blocks_needed(n);
+    int64_t scan_len = std::max<int64_t>(n + 1, 256 * std::max<int64_t>(c.sort_blocks, 1));
+    c.scan_tmp_len = scan_tmp_needed(scan_len);
+
+    hipError_t e = hipSuccess;
+#define A(ptr, cnt) if (e == hipSuccess) e = dalloc(c, &(ptr), (cnt))
+    A(c.d_sets, ns);
+    A(c.d_grp_set, grp_set.size());
+    A(c.d_bkt_set, bkt_set.size());
+    A(c.d_level_pref, pref.size());
+    A(c.d_key[0], n); A(c.d_key[1], n);
+    A(c.d_perm[0], n); A(c.d_perm[1], n);
+    A(c.d_hist, 2 * 256 * std::max<int64_t>(c.sort_blocks, 1));  // int64 view
+    A(c.d_bbox, 6 * ns);
+    A(c.xs, n); A(c.ys, n); A(c.zs, n); A(c.ms, n); A(c.Hs, n);
+    A(c.vxs, n); A(c.vys, n); A(c.vzs, n); A(c.us, n);
+    A(c.rhos, n); A(c.oms, n); A(c.As, n); A(c.css, n); A(c.Ps, n);
+    A(c.axs, n); A(c.ays, n); A(c.azs, n); A(c.dus, n); A(c.dts, n);
+    A(c.fxs, n); A(c.fys, n); A(c.fzs, n);
+    A(c.bref, 3 * std::max<int64_t>(c.nbuckets, 1));
+    A(c.nodes, c.nnodes);
+    A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
+    A(c.d_scan_tmp, c.scan_tmp_len);
+    A(c.d_cnt, C_NCOUNTERS);
+    A(c.d_rep, 1);
+    A(c.d_dt, 1);
+    A(c.d_part, 6 * reduce_partials());
+#undef A
+    if (e != hipSuccess) { free_all(c); return fail(x, SPH_ERR_OOM, "device allocation failed"); }
+    if (hipHostMalloc((void **)&c.h_cnt, sizeof(unsigned long long) * C_NCOUNTERS) != hipSuccess ||
+        hipHostMalloc((void **)&c.h_rep, sizeof(StepReport)) != hipSuccess) {
+        free_all(c);
+        return fail(x, SPH_ERR_OOM, "pinned allocation failed");
+    }
+    HIPCHK(x, hipMemcpyAsync(c.d_sets, sets.data(), sizeof(SetGeom) * ns, hipMemcpyHostToDevice, s), "sets");
+    if (!grp_set.empty())
+        HIPCHK(x, hipMemcpyAsync(c.d_grp_set, grp_set.data(), sizeof(int32_t) * grp_set.size(),
+                                 hipMemcpyHostToDevice, s), "groups");
+    if (!bkt_set.empty())
+        HIPCHK(x, hipMemcpyAsync(c.d_bkt_set, bkt_set.data(), sizeof(int32_t) * bkt_set.size(),
+                                 hipMemcpyHostToDevice, s), "buckets");
+    HIPCHK(x, hipMemcpyAsync(c.d_level_pref, pref.data(), sizeof(int64_t) * pref.size(),
+                             hipMemcpyHostToDevice, s), "levels");
+    HIPCHK(x, launch_init_nodes(&c, s), "init nodes");
+    HIPCHK(x, launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s), "counters");
+    HIPCHK(x, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_rep),
+                              sizeof(StepReport) / 8, 0ull, s), "report");
+    // host pages of the metadata vectors must outlive the copies
+    HIPCHK(x, hipStreamSynchronize(s), "setup sync");
+    c.n = n;
+    return SPH_OK;
+}
+
+sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs) {
+    if (!p) return fail(x, SPH_ERR_INVALID, "particles is NULL");
+    if (!p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->m || !p->u || !p->H)
+        return fail(x, SPH_ERR_INVALID, "a state array is NULL");
+    if (outputs && (!p->rho || !p->omega || !p->P || !p->c || !p->ax || !p->ay || !p->az ||
+                    !p->dudt || !p->dt))
+        return fail(x, SPH_ERR_INVALID, "an output array is NULL");
+    return SPH_OK;
+}
+
+hipError_t reset_counters(Ctx &c, hipStream_t s) {
+    return launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s);
+}
+
+Cols cols0() {
+    Cols k;
+    std::memset(&k, 0, sizeof(k));
+    return k;
+}
+
+// Density pass on the current tree; H first guess from the caller.
+sph_status do_density(sph_ctx *x, sph_particles *p, hipStream_t s) {
+    Ctx &c = x->c;
+    Cols g = cols0();
+    g.src[0] = p->H; g.dst[0] = c.Hs; g.n = 1;
+    HIPCHK(x, launch_gather(&c, g, s), "gather H");
+    HIPCHK(x, launch_density(&c, s), "density");
+    Cols o = cols0();
+    o.src[0] = c.Hs; o.dst[0] = p->H;
+    o.src[1] = c.rhos; o.dst[1] = p->rho;
+    o.src[2] = c.oms; o.dst[2] = p->omega;
+    o.n = 3;
+    HIPCHK(x, launch_scatter(&c, o, s), "scatter density");
+    HIPCHK(x, launch_refit(&c, s), "refit");
+    return SPH_OK;
+}
+
+// Force pass; velocities and u from the given columns (caller order).
+sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const double *vy,
+                     const double *vz, const double *u, bool gather_density, hipStream_t s) {
+    Ctx &c = x->c;
+    Cols g = cols0();
+    g.src[0] = vx; g.dst[0] = c.vxs;
+    g.src[1] = vy; g.dst[1] = c.vys;
+    g.src[2] = vz; g.dst[2] = c.vzs;
+    g.src[3] = u; g.dst[3] = c.us;
+    g.n = 4;
+    if (gather_density) {
+        g.src[4] = p->H; g.dst[4] = c.Hs;
+        g.src[5] = p->rho; g.dst[5] = c.rhos;
+        g.src[6] = p->omega; g.dst[6] = c.oms;
+        g.n = 7;
+    }
+    HIPCHK(x, launch_gather(&c, g, s), "gather force inputs");
+    if (gather_density) HIPCHK(x, launch_refit(&c, s), "refit");
+    HIPCHK(x, launch_eos(&c, c.us, p->P, p->c, s), "eos");
+    HIPCHK(x, launch_forces(&c, s), "forces");
+    Cols o = cols0();
+    o.src[0] = c.axs; o.dst[0] = p->ax;
+    o.src[1] = c.ays; o.dst[1] = p->ay;
+    o.src[2] = c.azs; o.dst[2] = p->az;
+    o.src[3] = c.dus; o.dst[3] = p->dudt;
+    o.src[4] = c.dts; o.dst[4] = p->dt;
+    o.n = 5;
+    HIPCHK(x, launch_scatter(&c, o, s), "scatter forces");
+    return SPH_OK;
+}
+
+sph_status do_step(sph_ctx *x, sph_particles *p, double dt, hipStream_t s) {
+    Ctx &c = x->c;
+    HIPCHK(x, reset_counters(c, s), "counters");
+    HIPCHK(x, launch_set_dt(&c, dt, s), "dt");
+    HIPCHK(x, launch_kick_drift(&c, p, s), "kick-drift");
+    HIPCHK(x, launch_tree_build(&c, p, s), "tree");
+    sph_status st = do_density(x, p, s);
+    if (st != SPH_OK) return st;
+    st = do_forces(x, p, c.vpx, c.vpy, c.vpz, c.upred, false, s);
+    if (st != SPH_OK) return st;
+    HIPCHK(x, launch_closing_kick(&c, p, s), "closing kick");
+    HIPCHK(x, launch_reduce(&c, p, s), "reduce");
+    return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sph_default_params(sph_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->kernel = SPH_KERNEL_M4;
+    p->precision = SPH_PREC_FP64;
+    p->eos = SPH_EOS_IDEAL;
+    p->periodic = 1;
+    p->n_ngb = 64.0;
+    for (int a = 0; a < 3; ++a) { p->box_lo[a] = 0.0; p->box_hi[a] = 1.0; }
+    p->gamma = 5.0 / 3.0;
+    p->P0 = 0.0;
+    p->alpha = 1.0;
+    p->beta = 2.0;
+    p->eps_av = 0.01;
+    p->eta_c = 0.3;
+    p->eta_a = 0.2;
+    p->dt_max = 1.0;
+    p->h_max = 0.25;
+    p->oversel = 1.1;
+    p->nr_tol = 0.0;
+    p->nr_maxit = 64;
+    p->bucket = 32;
+}
+
+const char *sph_version(void) { return kVersion; }
+
+const char *sph_last_error(const sph_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64_t *set_offsets,
+                            const double *set_box, sph_ctx **out) {
+    if (!out) return SPH_ERR_INVALID;
+    *out = nullptr;
+    std::string why;
+    if (!valid_params(params, why)) return SPH_ERR_INVALID;
+    if (nsets < 1 || nsets > 4096) return SPH_ERR_INVALID;
+    if (nsets > 1 && !set_offsets) return SPH_ERR_INVALID;
+    if (set_offsets) {
+        if (set_offsets[0] != 0) return SPH_ERR_INVALID;
+        for (int q = 0; q < nsets; ++q)
+            if (set_offsets[q + 1] < set_offsets[q]) return SPH_ERR_INVALID;
+        if (set_offsets[nsets] > ((int64_t)1 << 31) - 1) return SPH_ERR_INVALID;
+    }
+    if (set_box) {
+        for (int q = 0; q < nsets; ++q)
+            for (int a = 0; a < 3; ++a)
+                if (params->periodic && !(set_box[6 * q + 3 + a] > set_box[6 * q + a]))
+                    return SPH_ERR_INVALID;
+    }
+    sph_ctx *x = new (std::nothrow) sph_ctx();
+    if (!x) return SPH_ERR_OOM;
+    Ctx &c = x->c;
+    c.prm = *params;
+    if (!(c.prm.nr_tol > 0))
+        c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-6 : 1e-14;
+    c.bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    c.nsets = nsets;
+    if (set_offsets) c.set_off.assign(set_offsets, set_offsets + nsets + 1);
+    if (set_box) c.set_box.assign(set_box, set_box + 6 * nsets);
+    *out = x;
+    return SPH_OK;
+}
+
+sph_status sph_create(const sph_params *params, sph_ctx **out) {
+    return sph_create_batch(params, 1, nullptr, nullptr, out);
+}
+
+void sph_destroy(sph_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    free_all(ctx->c);
+    delete ctx;
+}
+
+sph_status sph_build_tree(sph_ctx *ctx, const sph_particles *p, int64_t n, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    sph_status st = check_particles(ctx, p, false);
+    if (st != SPH_OK) return st;
+    if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(ctx, SPH_ERR_INVALID, "bad n");
+    if (c.nsets == 1) {
+        c.set_off.assign({0, n});
+    } else if (c.set_off.back() != n) {
+        return fail(ctx, SPH_ERR_INVALID, "n differs from the batch total");
+    }
+    st = setup(ctx, n, s);
+    if (st != SPH_OK) return st;
+    c.last_stream = s;
+    if (n > 0) HIPCHK(ctx, launch_tree_build(&c, p, s), "tree build");
+    c.have_tree = true;
+    return SPH_OK;
+}
+
+sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int64_t *offsets,
+                         int32_t *idx, int64_t capacity, int64_t *needed, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
+    if (!offsets || !needed || (mode != SPH_MODE_GATHER && mode != SPH_MODE_FORCE))
+        return fail(ctx, SPH_ERR_INVALID, "bad neighbour arguments");
+    (void)p;
+    c.last_stream = s;
+    HIPCHK(ctx, reset_counters(c, s), "counters");
+    // counts into offsets[0..n-1], offsets[n] = 0, then exclusive scan in place
+    HIPCHK(ctx, launch_fill_u64(reinterpret_cast<unsigned long long *>(offsets), c.n + 1, 0ull, s),
+           "fill");
+    HIPCHK(ctx, launch_neighbors(&c, mode, offsets, nullptr, nullptr, s), "count");
+    HIPCHK(ctx, launch_scan_i64(&c, offsets, offsets, c.n + 1, s), "scan");
+    int64_t total = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&total, offsets + c.n, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+           "total");
+    HIPCHK(ctx, hipStreamSynchronize(s), "sync");
+    *needed = total;
+    if (total > capacity || (!idx && total > 0))
+        return fail(ctx, SPH_ERR_CAPACITY, "idx capacity below the number of pairs");
+    if (total > 0) {
+        HIPCHK(ctx, launch_neighbors(&c, mode, nullptr, offsets, idx, s), "fill");
+        HIPCHK(ctx, launch_sort_rows(&c, offsets, idx, s), "sort rows");
+    }
+    HIPCHK(ctx, hipMemcpyAsync(c.h_cnt, c.d_cnt, sizeof(unsigned long long) * C_NCOUNTERS,
+                               hipMemcpyDeviceToHost, s), "counters");
+    HIPCHK(ctx, hipStreamSynchronize(s), "sync");
+    if (c.h_cnt[C_OVERFLOW]) return fail(ctx, SPH_ERR_CAPACITY, "walk stack overflow");
+    if (c.h_cnt[C_ROWLONG]) return fail(ctx, SPH_ERR_CAPACITY, "a row exceeds 4096 entries");
+    return SPH_OK;
+}
+
+sph_status sph_density(sph_ctx *ctx, sph_particles *p, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
+    sph_status st = check_particles(ctx, p, true);
+    if (st != SPH_OK) return st;
+    c.last_stream = s;
+    HIPCHK(ctx, reset_counters(c, s), "counters");
+    return do_density(ctx, p, s);
+}
+
+sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
+    sph_status st = check_particles(ctx, p, true);
+    if (st != SPH_OK) return st;
+    c.last_stream = s;
+    HIPCHK(ctx, reset_counters(c, s), "counters");
+    st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, true, s);
+    if (st != SPH_OK) return st;
+    HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
+    c.have_forces = true;
+    return SPH_OK;
+}
+
+sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    sph_status st = check_particles(ctx, p, true);
+    if (st != SPH_OK) return st;
+    st = sph_build_tree(ctx, p, n, stream);
+    if (st != SPH_OK) return st;
+    HIPCHK(ctx, reset_counters(c, s), "counters");
+    st = do_density(ctx, p, s);
+    if (st != SPH_OK) return st;
+    st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, false, s);
+    if (st != SPH_OK) return st;
+    HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
+    c.have_forces = true;
+    return SPH_OK;
+}
+
+sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    if (!c.have_forces) return fail(ctx, SPH_ERR_STATE, "call sph_init before sph_step");
+    sph_status st = check_particles(ctx, p, true);
+    if (st != SPH_OK) return st;
+    if (!(dt == dt)) return fail(ctx, SPH_ERR_INVALID, "dt is NaN");
+    c.last_stream = s;
+    return do_step(ctx, p, dt, s);
+}
+
+sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    if (!c.have_forces) return fail(ctx, SPH_ERR_STATE, "call sph_init before capturing a step");
+    sph_status st = check_particles(ctx, p, true);
+    if (st != SPH_OK) return st;
+    if (!s) return fail(ctx, SPH_ERR_INVALID, "graph capture needs a non-null stream");
+    if (c.graph_exec) { (void)hipGraphExecDestroy(c.graph_exec); c.graph_exec = nullptr; }
+    if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
+    HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    st = do_step(ctx, p, dt, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != SPH_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+    c.graph = g;
+    HIPCHK(ctx, hipGraphInstantiate(&c.graph_exec, g, nullptr, nullptr, 0), "instantiate");
+    return SPH_OK;
+}
+
+sph_status sph_graph_launch(sph_ctx *ctx, void *stream) {
+    if (!ctx) return SPH_ERR_INVALID;
+    Ctx &c = ctx->c;
+    if (!c.graph_exec) return fail(ctx, SPH_ERR_STATE, "no captured graph");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    c.last_stream = s;
+    HIPCHK(ctx, hipGraphLaunch(c.graph_exec, s), "graph launch");
+    return SPH_OK;
+}
+
+sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
+    if (!ctx || !out) return SPH_ERR_INVALID;
+    Ctx &c = ctx->c;
+    std::memset(out, 0, sizeof(*out));
+    out->n = c.n;
+    if (!c.d_cnt) return SPH_OK;
+    HIPCHK(ctx, hipStreamSynchronize(c.last_stream), "sync");
+    HIPCHK(ctx, hipMemcpy(c.h_cnt, c.d_cnt, sizeof(unsigned long long) * C_NCOUNTERS,
+                          hipMemcpyDeviceToHost), "counters");
+    HIPCHK(ctx, hipMemcpy(c.h_rep, c.d_rep, sizeof(StepReport), hipMemcpyDeviceToHost), "report");
+    out->pairs_density = (int64_t)c.h_cnt[C_PAIRS_D];
+    out->pairs_force = (int64_t)c.h_cnt[C_PAIRS_F];
+    out->cand_density = (int64_t)c.h_cnt[C_CAND_D];
+    out->cand_force = (int64_t)c.h_cnt[C_CAND_F];
+    out->nr_iter_max = (int64_t)c.h_cnt[C_NR_ITER_MAX];
+    out->nr_scans = (int64_t)c.h_cnt[C_NR_SCANS];
+    out->n_noconv = (int64_t)c.h_cnt[C_NOCONV];
+    out->n_rewalk = (int64_t)c.h_cnt[C_REWALK];
+    out->n_overflow = (int64_t)c.h_cnt[C_OVERFLOW];
+    for (int a = 0; a < 3; ++a) out->momentum[a] = c.h_rep->momentum[a];
+    out->e_kin = c.h_rep->e_kin;
+    out->e_int = c.h_rep->e_int;
+    out->dt_next = c.h_rep->dt_next;
+    out->dt_used = c.h_rep->dt_used;
+    return SPH_OK;
+}
+
+sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *stream) {
+    (void)ctx; (void)p; (void)bucket; (void)stream;
+    return SPH_ERR_STATE;
+}
+
+}  // extern "C"

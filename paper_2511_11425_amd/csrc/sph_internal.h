@@ -1,0 +1,159 @@
+// sph_internal.h -- internal declarations of the MI355X SPH sweep library.
+// Device helpers, the context object and the launch wrappers shared by the
+// translation units of the library.  Nothing here is part of the C interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sph.h"
+
+namespace sphmi {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kGroup = 64;         // sink group: one wavefront, one particle per lane
+constexpr int kStackCap = 1536;    // per-wave walk stack (node ids) in LDS
+constexpr int kCandCap = 512;      // per-wave candidate-bucket list in LDS
+constexpr int kMaxRow = 4096;      // longest neighbour row sph_neighbors can sort
+
+// Device counters of the most recent call (all 64-bit, summed with integer
+// atomics so totals do not depend on scheduling).
+enum Counter {
+    C_PAIRS_D = 0, C_PAIRS_F, C_CAND_D, C_CAND_F, C_NR_ITER_MAX, C_NR_SCANS,
+    C_NOCONV, C_REWALK, C_OVERFLOW, C_ROWLONG, C_NCOUNTERS
+};
+
+// FP64 results of the last step (device), copied into sph_stats.
+struct StepReport {
+    double momentum[3];
+    double e_kin, e_int;
+    double dt_next;   // min_i dt_i of the last force pass, capped by dt_max
+    double dt_used;   // dt of the last step
+    double pad;
+};
+
+// Per-set geometry shared by all kernels (device array, one entry per set).
+struct SetGeom {
+    double lo[3];     // box low corner (periodic) or key box (open)
+    double L[3];      // box lengths (periodic) or key-box lengths (open)
+    double halfL[3];  // L/2 (exact)
+    int64_t p0, p1;   // particle range [p0, p1) (sorted order == caller set range)
+    int64_t b0;       // first global bucket of the set
+    int64_t g0;       // first global sink group of the set
+    int64_t node0;    // node slot of heap index 0 (slots node0 + 1 .. node0 + 2*nbp - 1)
+    int32_t nb;       // buckets in the set
+    int32_t nbp;      // nb rounded up to a power of two (leaf count of the heap)
+    int32_t depth;    // log2(nbp)
+    int32_t pad;
+};
+
+// One tree node: cell bound (AABB of positions), box-of-balls (AABB of the
+// kernel balls) and ball-of-balls (an enclosing sphere of the kernel balls),
+// Sec. 2.3.2 and Fig. 1.  Empty nodes have clo > chi.
+struct Node {
+    double clo[3], chi[3];
+    double blo[3], bhi[3];
+    double bc[3], br;
+};
+
+struct Ctx {
+    sph_params prm{};
+    int32_t nsets = 1;
+    std::vector<int64_t> set_off;   // host, nsets+1
+    std::vector<double> set_box;    // host, 6*nsets (empty = params box)
+    int32_t bucket = 32;
+    int64_t n = 0;                  // particles of the current allocation
+    int64_t nbuckets = 0, ngroups = 0, nnodes = 0;
+    int32_t max_depth = 0;
+    int32_t key_passes = 0;         // radix passes of 8 bits
+    int32_t set_bits = 0;
+    bool have_tree = false, have_forces = false;
+    std::string err;
+    hipStream_t last_stream = nullptr;
+
+    // topology (device)
+    SetGeom *d_sets = nullptr;
+    int32_t *d_grp_set = nullptr;   // per group: set id
+    int32_t *d_bkt_set = nullptr;   // per bucket: set id
+    int64_t *d_level_pref = nullptr;// (max_depth+1) x (nsets+1) prefix of nodes per height
+    std::vector<int64_t> level_total;
+
+    // sort
+    uint64_t *d_key[2] = {nullptr, nullptr};
+    uint32_t *d_perm[2] = {nullptr, nullptr};
+    uint32_t *d_hist = nullptr;     // 256 x sort blocks
+    int64_t sort_blocks = 0;
+    double *d_bbox = nullptr;       // per set: open-boundary key box (6 doubles)
+
+    // sorted particle data (FP64)
+    double *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr, *Hs = nullptr;
+    double *vxs = nullptr, *vys = nullptr, *vzs = nullptr, *us = nullptr;
+    double *rhos = nullptr, *oms = nullptr, *As = nullptr, *css = nullptr, *Ps = nullptr;
+    double *axs = nullptr, *ays = nullptr, *azs = nullptr, *dus = nullptr, *dts = nullptr;
+    // FP32 bucket-relative offsets for the mixed path
+    float *fxs = nullptr, *fys = nullptr, *fzs = nullptr;
+    double *bref = nullptr;         // per bucket: reference point (3 doubles)
+
+    Node *nodes = nullptr;
+
+    // predictor scratch (caller order) for the step
+    double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *upred = nullptr;
+
+    // scan scratch
+    int64_t *d_scan_tmp = nullptr;
+    int64_t scan_tmp_len = 0;
+
+    // counters, step report, reduction partials
+    unsigned long long *d_cnt = nullptr;
+    StepReport *d_rep = nullptr;
+    double *d_dt = nullptr;         // step size used by the kick kernels
+    double *d_part = nullptr;       // reduction partials
+    unsigned long long *h_cnt = nullptr; // pinned host mirrors
+    StepReport *h_rep = nullptr;
+
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    std::vector<void *> allocs;
+};
+
+// ---------------------------------------------------------------- launches
+// Tree (sph_tree.hip)
+hipError_t launch_tree_build(Ctx *c, const sph_particles *p, hipStream_t s);
+hipError_t launch_refit(Ctx *c, hipStream_t s);
+hipError_t launch_init_nodes(Ctx *c, hipStream_t s);
+hipError_t launch_scan_i64(Ctx *c, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+int64_t scan_tmp_needed(int64_t n);
+int64_t sort_blocks_needed(int64_t n);
+int morton_bits();
+
+// Sweep (sph_sweep.hip)
+hipError_t launch_density(Ctx *c, hipStream_t s);
+hipError_t launch_forces(Ctx *c, hipStream_t s);
+hipError_t launch_neighbors(Ctx *c, int mode, int64_t *row_count_caller, const int64_t *offsets,
+                            int32_t *idx, hipStream_t s);
+hipError_t launch_sort_rows(Ctx *c, const int64_t *offsets, int32_t *idx, hipStream_t s);
+
+// Elementwise, step, reductions (sph_kdk.hip)
+constexpr int kMaxCols = 8;
+struct Cols {
+    const double *src[kMaxCols];
+    double *dst[kMaxCols];
+    int n;
+};
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_gather(Ctx *c, const Cols &cols, hipStream_t s);   // dst[k] = src[perm[k]]
+hipError_t launch_scatter(Ctx *c, const Cols &cols, hipStream_t s);  // dst[perm[k]] = src[k]
+hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *c_caller,
+                      hipStream_t s);
+hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s);
+hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s);
+int reduce_partials();
+
+}  // namespace sphmi

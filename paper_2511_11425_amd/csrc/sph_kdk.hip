@@ -1,0 +1,269 @@
+// sph_kdk.hip -- elementwise passes of the step: gathers into and scatters out
+// of Morton order, the equation of state (Sec. 2.3.1), the kick-drift-kick
+// integrator with the velocity/energy predictor (Sec. 2.3.6), and the FP64
+// reductions of momentum, energy and the global time step.  All of these are
+// HBM-bound streams; they are kept separate from the sweep so the same
+// kernels serve the single-call interface and the captured step.
+#include "sph_internal.h"
+
+#include <cfloat>
+
+namespace sphmi {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRedBlocks = 512;
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_gather_cols(const uint32_t *__restrict__ perm, int64_t n, Cols c) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t i = perm[k];
+#pragma unroll
+    for (int q = 0; q < kMaxCols; ++q)
+        if (q < c.n) c.dst[q][k] = c.src[q][i];
+}
+
+__global__ void k_scatter_cols(const uint32_t *__restrict__ perm, int64_t n, Cols c) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t i = perm[k];
+#pragma unroll
+    for (int q = 0; q < kMaxCols; ++q)
+        if (q < c.n) c.dst[q][i] = c.src[q][k];
+}
+
+// EOS on sorted arrays: P, c and A = P / (Omega rho^2); P and c also go to
+// the caller's arrays.
+__global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, double gam, double P0,
+                      const double *__restrict__ rho, const double *__restrict__ u,
+                      const double *__restrict__ om, double *__restrict__ Ps,
+                      double *__restrict__ cs, double *__restrict__ As,
+                      double *__restrict__ Pc, double *__restrict__ cc) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double r = rho[k], uu = u[k];
+    double P, c2;
+    if (eos == SPH_EOS_IDEAL) {
+        P = (gam - 1.0) * r * uu;
+        c2 = gam * (gam - 1.0) * uu;
+    } else {
+        P = (gam - 1.0) * r * uu - gam * P0;
+        c2 = gam * (P + P0) / r;
+    }
+    double c = c2 > 0.0 ? sqrt(c2) : 0.0;
+    Ps[k] = P;
+    cs[k] = c;
+    As[k] = P / (om[k] * r * r);
+    uint32_t i = perm[k];
+    Pc[i] = P;
+    cc[i] = c;
+}
+
+__global__ void k_set_dt(double dt_in, double dt_max, const StepReport *rep, double *d_dt,
+                         StepReport *rep_out) {
+    double dt = dt_in > 0.0 ? dt_in : fmin(rep->dt_next, dt_max);
+    *d_dt = dt;
+    rep_out->dt_used = dt;
+}
+
+// Opening kick, predictor and drift in caller order (Sec. 2.3.6):
+//   v_half = v + (dt/2) a,  u_half = u + (dt/2) du      (stored in v, u)
+//   v_pred = v_half + (dt/2) a,  u_pred likewise          (scratch)
+//   x     += dt v_half, wrapped into the periodic box
+struct KickArgs {
+    double *x, *y, *z, *vx, *vy, *vz, *u;
+    const double *ax, *ay, *az, *du;
+    double *vpx, *vpy, *vpz, *up;
+    const SetGeom *sets;
+    int nsets;
+    int periodic;
+    const double *dt;
+    int64_t n;
+};
+
+__device__ inline int find_set_k(const SetGeom *sets, int nsets, int64_t i) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].p0 <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ double wrap_box(double v, double lo, double L) {
+#pragma clang fp contract(off)
+    double t = floor((v - lo) / L);
+    double s = L * t;
+    return v - s;
+}
+
+__global__ void k_kick_drift(KickArgs a) {
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double dt = *a.dt;
+    const double hdt = 0.5 * dt;
+    double ax = a.ax[i], ay = a.ay[i], az = a.az[i], du = a.du[i];
+    double vhx = a.vx[i] + hdt * ax;
+    double vhy = a.vy[i] + hdt * ay;
+    double vhz = a.vz[i] + hdt * az;
+    double uh = a.u[i] + hdt * du;
+    a.vx[i] = vhx; a.vy[i] = vhy; a.vz[i] = vhz; a.u[i] = uh;
+    a.vpx[i] = vhx + hdt * ax;
+    a.vpy[i] = vhy + hdt * ay;
+    a.vpz[i] = vhz + hdt * az;
+    a.up[i] = uh + hdt * du;
+    double nx = a.x[i] + dt * vhx;
+    double ny = a.y[i] + dt * vhy;
+    double nz = a.z[i] + dt * vhz;
+    if (a.periodic) {
+        const SetGeom &g = a.sets[a.nsets == 1 ? 0 : find_set_k(a.sets, a.nsets, i)];
+        nx = wrap_box(nx, g.lo[0], g.L[0]);
+        ny = wrap_box(ny, g.lo[1], g.L[1]);
+        nz = wrap_box(nz, g.lo[2], g.L[2]);
+    }
+    a.x[i] = nx; a.y[i] = ny; a.z[i] = nz;
+}
+
+// Closing kick: v = v_half + (dt/2) a_new, u likewise.
+__global__ void k_closing_kick(int64_t n, const double *__restrict__ dtp, double *vx, double *vy,
+                               double *vz, double *u, const double *__restrict__ ax,
+                               const double *__restrict__ ay, const double *__restrict__ az,
+                               const double *__restrict__ du) {
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double hdt = 0.5 * (*dtp);
+    vx[i] = vx[i] + hdt * ax[i];
+    vy[i] = vy[i] + hdt * ay[i];
+    vz[i] = vz[i] + hdt * az[i];
+    u[i] = u[i] + hdt * du[i];
+}
+
+// Deterministic two-stage FP64 reduction: fixed grid, fixed tree order.
+__global__ __launch_bounds__(kThreads) void k_reduce_part(int64_t n, const double *__restrict__ m,
+                                                          const double *__restrict__ vx,
+                                                          const double *__restrict__ vy,
+                                                          const double *__restrict__ vz,
+                                                          const double *__restrict__ u,
+                                                          const double *__restrict__ dt,
+                                                          double *__restrict__ part) {
+    __shared__ double sh[6][kThreads];
+    double acc[5] = {0, 0, 0, 0, 0};
+    double mn = DBL_MAX;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)kRedBlocks * kThreads) {
+        double mm = m[i], a = vx[i], b = vy[i], c = vz[i];
+        acc[0] += mm * a;
+        acc[1] += mm * b;
+        acc[2] += mm * c;
+        acc[3] += 0.5 * mm * (a * a + b * b + c * c);
+        acc[4] += mm * u[i];
+        mn = fmin(mn, dt[i]);
+    }
+    for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = acc[q];
+    sh[5][threadIdx.x] = mn;
+    __syncthreads();
+    for (int st = kThreads / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+            sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kRedBlocks) void k_reduce_final(const double *__restrict__ part,
+                                                             double dt_max, StepReport *rep) {
+    __shared__ double sh[6][kRedBlocks];
+    for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] = part[threadIdx.x * 6 + q];
+    __syncthreads();
+    for (int st = kRedBlocks / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+            sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rep->momentum[0] = sh[0][0];
+        rep->momentum[1] = sh[1][0];
+        rep->momentum[2] = sh[2][0];
+        rep->e_kin = sh[3][0];
+        rep->e_int = sh[4][0];
+        rep->dt_next = fmin(sh[5][0], dt_max);
+    }
+}
+
+}  // namespace
+
+int reduce_partials() { return kRedBlocks; }
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_u64<<<nblk(n, kThreads), kThreads, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(Ctx *c, const Cols &cols, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_gather_cols<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->n, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(Ctx *c, const Cols &cols, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_scatter_cols<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->n, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *c_caller,
+                      hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_eos<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->n, c->prm.eos, c->prm.gamma,
+                                                    c->prm.P0, c->rhos, u_sorted, c->oms, c->Ps,
+                                                    c->css, c->As, P_caller, c_caller);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s) {
+    k_set_dt<<<1, 1, 0, s>>>(dt, c->prm.dt_max, c->d_rep, c->d_dt, c->d_rep);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    KickArgs a;
+    a.x = p->x; a.y = p->y; a.z = p->z; a.vx = p->vx; a.vy = p->vy; a.vz = p->vz; a.u = p->u;
+    a.ax = p->ax; a.ay = p->ay; a.az = p->az; a.du = p->dudt;
+    a.vpx = c->vpx; a.vpy = c->vpy; a.vpz = c->vpz; a.up = c->upred;
+    a.sets = c->d_sets; a.nsets = c->nsets; a.periodic = c->prm.periodic;
+    a.dt = c->d_dt; a.n = c->n;
+    k_kick_drift<<<nblk(c->n, kThreads), kThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_closing_kick<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->d_dt, p->vx, p->vy, p->vz,
+                                                             p->u, p->ax, p->ay, p->az, p->dudt);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s) {
+    k_reduce_part<<<kRedBlocks, kThreads, 0, s>>>(c->n, p->m, p->vx, p->vy, p->vz, p->u, p->dt,
+                                                   c->d_part);
+    k_reduce_final<<<1, kRedBlocks, 0, s>>>(c->d_part, c->prm.dt_max, c->d_rep);
+    return hipGetLastError();
+}
+
+}  // namespace sphmi

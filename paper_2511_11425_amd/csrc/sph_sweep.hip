@@ -1,0 +1,869 @@
+// sph_sweep.hip -- the neighbour-interaction sweep on gfx950.
+//
+//   walk      one wavefront per sink group of 64 consecutive (Morton-ordered)
+//             particles walks its set's bucket tree with the bound-overlap
+//             tests of Sec. 2.3.2 / Fig. 1: gather = sink box-of-balls AND
+//             sink ball-of-balls overlap the source cell bound; scatter =
+//             source box-of-balls AND ball-of-balls overlap the sink cell
+//             bound.  64 nodes are tested per step (one per lane); accepted
+//             children are pushed and accepted buckets appended to an LDS
+//             candidate list by ballot + popcount compaction.  The list holds
+//             whole buckets; pairs are selected later (Sec. 2.3.2: lists are
+//             not pruned pairwise during the walk).
+//   density   candidate buckets are staged 64 particles at a time into LDS;
+//             each lane (one sink particle) tests r^2 < H_i^2 against the
+//             broadcast tile and accumulates the density sum and dH-derivative
+//             (eq:Density_estimate).  The Newton iteration on H (Sec. 2.3.3)
+//             re-scans the same candidate list; the walk used oversel*H so H
+//             can grow, and a group whose H outgrows it is re-walked.
+//   forces    same structure over the gather-or-scatter list with the
+//             symmetrised pressure force, PdV du/dt, Monaghan viscosity and
+//             the time-step limits (Sec. 2.3.5, 2.3.6).
+//
+// Precision: FP64 path = every pair operation in FP64 with the pair distance
+// evaluated as (dx*dx + dy*dy) + dz*dz without contraction, so neighbour
+// sets are reproducible bit for bit.  Mixed path = pair arithmetic in FP32 on
+// coordinates relative to the sink group's centre (formed in FP64, rounded
+// once per staged candidate), per-tile FP32 partial sums folded into
+// Neumaier-compensated FP32 accumulators; H iteration bookkeeping, positions
+// and outputs stay FP64.
+#include "sph_internal.h"
+
+#include <cfloat>
+#include <type_traits>
+
+namespace sphmi {
+
+namespace {
+
+// ---------------------------------------------------------------- kernels
+constexpr double kPi = 3.14159265358979323846;
+
+template <int K> __device__ __forceinline__ double sigma_of() {
+    return K == 0 ? 8.0 / kPi : K == 1 ? 21.0 / (2.0 * kPi) : K == 2 ? 495.0 / (32.0 * kPi)
+                                                                   : 1365.0 / (64.0 * kPi);
+}
+
+// f(q) and q f'(q) on 0 <= q <= 1 (s clamped so rounding at q ~ 1 stays harmless).
+template <int K, typename R>
+__device__ __forceinline__ void shape_f_qfp(R q, R &f, R &qfp) {
+    R s = R(1) - q;
+    s = s > R(0) ? s : R(0);
+    if constexpr (K == 0) {
+        if (q < R(0.5)) {
+            f = R(1) + q * q * (R(6) * q - R(6));
+            qfp = q * q * (R(18) * q - R(12));
+        } else {
+            f = R(2) * s * s * s;
+            qfp = R(-6) * q * s * s;
+        }
+    } else if constexpr (K == 1) {
+        R s3 = s * s * s;
+        f = s3 * s * (R(1) + R(4) * q);
+        qfp = R(-20) * q * q * s3;
+    } else if constexpr (K == 2) {
+        R s2 = s * s, s5 = s2 * s2 * s;
+        f = s5 * s * (R(1) + q * (R(6) + q * R(35.0 / 3.0)));
+        qfp = R(-56.0 / 3.0) * q * q * s5 * (R(1) + R(5) * q);
+    } else {
+        R s2 = s * s, s4 = s2 * s2, s7 = s4 * s2 * s;
+        f = s7 * s * (R(1) + q * (R(8) + q * (R(25) + q * R(32))));
+        qfp = R(-22) * q * q * s7 * (R(1) + q * (R(7) + q * R(16)));
+    }
+}
+
+// g(q) = f'(q)/q.  The outer cubic-spline piece (q >= 1/2, so r > 0) needs
+// 1/q = H/r; it is formed only in that branch.
+template <int K, typename R>
+__device__ __forceinline__ R shape_g(R q, R H, R r) {
+    R s = R(1) - q;
+    s = s > R(0) ? s : R(0);
+    if constexpr (K == 0) {
+        if (q < R(0.5)) return R(18) * q - R(12);
+        return R(-6) * s * s * (H / r);
+    } else if constexpr (K == 1) {
+        return R(-20) * s * s * s;
+    } else if constexpr (K == 2) {
+        R s2 = s * s;
+        return R(-56.0 / 3.0) * s2 * s2 * s * (R(1) + R(5) * q);
+    } else {
+        R s2 = s * s, s4 = s2 * s2;
+        return R(-22) * s4 * s2 * s * (R(1) + q * (R(7) + q * R(16)));
+    }
+}
+
+// ---------------------------------------------------------------- geometry
+
+__device__ __forceinline__ double min_image(double d, double L, double hL) {
+    if (d > hL) return d - L;
+    if (d < -hL) return d + L;
+    return d;
+}
+
+// r^2 = (dx*dx + dy*dy) + dz*dz without FMA contraction (reproducible membership).
+__device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    double r2 = dx * dx + dy * dy;
+    r2 = r2 + dz * dz;
+    return r2;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+struct Sink {
+    double clo[3], chi[3];  // cell bound of the group
+    double blo[3], bhi[3];  // box of the balls of radius Hw
+    double bc[3], br;       // enclosing sphere of the balls
+};
+
+__device__ inline void sink_bounds(bool act, const double *x, double Hw, Sink &sk) {
+    for (int a = 0; a < 3; ++a) {
+        sk.clo[a] = wave_min(act ? x[a] : DBL_MAX);
+        sk.chi[a] = wave_max(act ? x[a] : -DBL_MAX);
+        sk.blo[a] = wave_min(act ? x[a] - Hw : DBL_MAX);
+        sk.bhi[a] = wave_max(act ? x[a] + Hw : -DBL_MAX);
+        sk.bc[a] = 0.5 * (sk.clo[a] + sk.chi[a]);
+    }
+    double r = 0.0;
+    if (act) {
+        double dx = x[0] - sk.bc[0], dy = x[1] - sk.bc[1], dz = x[2] - sk.bc[2];
+        r = sqrt(dx * dx + dy * dy + dz * dz) + Hw;
+    }
+    sk.br = wave_max(r) * (1.0 + 1e-12);
+}
+
+// Distance between interval centres along one axis (minimum image when periodic).
+__device__ __forceinline__ double cdist(double ca, double cb, double L, double hL, bool per) {
+    double d = cb - ca;
+    if (per) d = min_image(d, L, hL);
+    return fabs(d);
+}
+
+__device__ __forceinline__ bool box_box(const double *alo, const double *ahi, const double *blo,
+                                        const double *bhi, const SetGeom &g, bool per, double slop) {
+    for (int a = 0; a < 3; ++a) {
+        if (!(blo[a] <= bhi[a]) || !(alo[a] <= ahi[a])) return false;
+        double ca = 0.5 * (alo[a] + ahi[a]), wa = 0.5 * (ahi[a] - alo[a]);
+        double cb = 0.5 * (blo[a] + bhi[a]), wb = 0.5 * (bhi[a] - blo[a]);
+        if (cdist(ca, cb, g.L[a], g.halfL[a], per) - wa - wb > slop) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool ball_box(const double *c, double R, const double *blo,
+                                         const double *bhi, const SetGeom &g, bool per, double slop) {
+    if (!(R >= 0.0)) return false;
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (!(blo[a] <= bhi[a])) return false;
+        double cb = 0.5 * (blo[a] + bhi[a]), wb = 0.5 * (bhi[a] - blo[a]);
+        double gap = cdist(c[a], cb, g.L[a], g.halfL[a], per) - wb;
+        gap = gap > 0.0 ? gap : 0.0;
+        d2 += gap * gap;
+    }
+    double Rs = R + slop;
+    return d2 <= Rs * Rs;
+}
+
+// Walk state lives in LDS (stack, candidate list) and in wave-uniform registers.
+struct WalkState {
+    int nstack;
+    int ncand;
+    bool overflow;
+};
+
+__device__ __forceinline__ void walk_reset(uint32_t *stack, WalkState &w) {
+    if (threadIdx.x == 0) stack[0] = 1u;
+    w.nstack = 1;
+    w.ncand = 0;
+    __syncthreads();
+}
+
+// Continue the walk until the stack is empty or the candidate list is nearly
+// full (the caller consumes it and calls again).
+template <bool SCATTER>
+__device__ void walk(const SetGeom &g, bool per, double slop, const Node *__restrict__ nodes,
+                     const Sink &sk, uint32_t *stack, uint32_t *cand, WalkState &w) {
+    const int lane = threadIdx.x;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    while (w.nstack > 0 && w.ncand <= kCandCap - kWave) {
+        int k = w.nstack < kWave ? w.nstack : kWave;
+        if (w.nstack + k > kStackCap) k = kStackCap - w.nstack;
+        if (k <= 0) { w.overflow = true; w.nstack = 0; break; }
+        const int base = w.nstack - k;
+        uint32_t h = lane < k ? stack[base + lane] : 0u;
+        __syncthreads();
+        bool ok = false;
+        if (lane < k) {
+            const Node *nd = nodes + g.node0 + h;
+            double clo[3] = {nd->clo[0], nd->clo[1], nd->clo[2]};
+            double chi[3] = {nd->chi[0], nd->chi[1], nd->chi[2]};
+            ok = box_box(sk.blo, sk.bhi, clo, chi, g, per, slop) &&
+                 ball_box(sk.bc, sk.br, clo, chi, g, per, slop);
+            if (SCATTER && !ok) {
+                double blo[3] = {nd->blo[0], nd->blo[1], nd->blo[2]};
+                double bhi[3] = {nd->bhi[0], nd->bhi[1], nd->bhi[2]};
+                double bc[3] = {nd->bc[0], nd->bc[1], nd->bc[2]};
+                ok = box_box(blo, bhi, sk.clo, sk.chi, g, per, slop) &&
+                     ball_box(bc, nd->br, sk.clo, sk.chi, g, per, slop);
+            }
+        }
+        const bool leaf = h >= (uint32_t)g.nbp;
+        const bool inner_ok = ok && !leaf;
+        const bool leaf_ok = ok && leaf && (h - (uint32_t)g.nbp) < (uint32_t)g.nb;
+        const uint64_t m1 = __ballot(inner_ok);
+        const uint64_t m2 = __ballot(leaf_ok);
+        if (inner_ok) {
+            int p = __popcll(m1 & lt);
+            stack[base + 2 * p] = 2u * h;
+            stack[base + 2 * p + 1] = 2u * h + 1u;
+        }
+        if (leaf_ok) {
+            int p = __popcll(m2 & lt);
+            cand[w.ncand + p] = (uint32_t)(g.b0 + (int64_t)(h - (uint32_t)g.nbp));
+        }
+        w.nstack = base + 2 * __popcll(m1);
+        w.ncand += __popcll(m2);
+        __syncthreads();
+    }
+}
+
+// Neumaier-compensated accumulation (FP32 partial sums of the mixed path).
+__device__ __forceinline__ void neumaier(float &sum, float &comp, float v) {
+    float t = sum + v;
+    if (fabsf(sum) >= fabsf(v)) comp += (sum - t) + v;
+    else comp += (v - t) + sum;
+    sum = t;
+}
+
+struct SweepArgs {
+    const SetGeom *sets;
+    const int32_t *grp_set;
+    const Node *nodes;
+    const uint32_t *perm;
+    const double *xs, *ys, *zs, *ms;
+    double *Hs, *rhos, *oms;
+    const double *vxs, *vys, *vzs, *As, *css;
+    double *ax, *ay, *az, *du, *dt;
+    unsigned long long *cnt;
+    int B;
+    int periodic;
+    double oversel, tol, h_max, n_ngb;
+    int maxit;
+    double alpha, beta, eps, eta_a, eta_c, dt_max;
+    // neighbour lists
+    int64_t *row_count;     // caller order (count pass)
+    const int64_t *offsets; // caller order (fill pass)
+    int32_t *idx;
+};
+
+__device__ __forceinline__ double set_slop(const SetGeom &g) {
+    return 1e-9 * (g.L[0] + g.L[1] + g.L[2]);
+}
+__device__ __forceinline__ double set_hcap(const SetGeom &g, bool per, double h_max) {
+    if (!per) return h_max;
+    double lm = fmin(g.L[0], fmin(g.L[1], g.L[2]));
+    return fmin(h_max, 0.5 * lm);
+}
+
+// Stage 64 candidate slots starting at candidate-list position t0 (64/B
+// buckets).  Returns the sorted particle index of this lane's slot or -1.
+__device__ __forceinline__ int64_t slot_index(const SetGeom &g, const uint32_t *cand, int ncand,
+                                              int t0, int B) {
+    const int lane = threadIdx.x;
+    int bi = t0 + lane / B;
+    int off = lane % B;
+    if (bi >= ncand) return -1;
+    int64_t b = cand[bi];
+    int64_t start = g.p0 + (b - g.b0) * B;
+    int64_t j = start + off;
+    return j < g.p1 ? j : -1;
+}
+
+// ================================================================ density
+
+template <int K, bool MIXED>
+__global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
+    __shared__ uint32_t stack[kStackCap];
+    __shared__ uint32_t cand[kCandCap];
+    typedef typename std::conditional<MIXED, float, double>::type R;
+    __shared__ R tx[kWave], ty[kWave], tz[kWave], tm[kWave];
+
+    const int lane = threadIdx.x;
+    const int64_t grp = blockIdx.x;
+    const int sid = a.grp_set[grp];
+    const SetGeom g = a.sets[sid];
+    const bool per = a.periodic != 0;
+    const double slop = set_slop(g);
+    const double cap = set_hcap(g, per, a.h_max);
+    const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
+    const bool act = i < g.p1;
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    const double mi = act ? a.ms[i] : 0.0;
+    double H = act ? a.Hs[i] : 0.0;
+    if (!(H > 0.0)) H = 0.01 * cap;
+    if (H > cap) H = cap;
+    const double target = a.n_ngb * mi;
+    const double sig = sigma_of<K>();
+    const double c43 = 4.0 * kPi / 3.0;
+
+    double lo = 0.0, hi = 0.0;
+    bool hi_ok = false;
+    bool done = !act;
+    bool noconv = false;
+    double Hw = fmin(a.oversel * H, cap);
+    double rho = 0.0, om = 1.0;
+    int cnt_out = 0;
+
+    // group reference point for the mixed path (cell centre of the group)
+    double gc[3];
+    for (int q = 0; q < 3; ++q) {
+        double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
+        gc[q] = 0.5 * (mn + mx);
+    }
+    R qx = 0, qy = 0, qz = 0;
+    if constexpr (MIXED) {
+        qx = (R)(per ? min_image(xi[0] - gc[0], g.L[0], g.halfL[0]) : xi[0] - gc[0]);
+        qy = (R)(per ? min_image(xi[1] - gc[1], g.L[1], g.halfL[1]) : xi[1] - gc[1]);
+        qz = (R)(per ? min_image(xi[2] - gc[2], g.L[2], g.halfL[2]) : xi[2] - gc[2]);
+    }
+
+    WalkState ws{0, 0, false};
+    Sink sk;
+    bool list_complete = false;
+    int scans = 0, rewalks = 0;
+    unsigned long long cand_tested = 0;
+    bool need_walk = true;
+
+    while (true) {
+        if (need_walk) {
+            sink_bounds(act, xi, Hw, sk);
+            walk_reset(stack, ws);
+            walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+            list_complete = (ws.nstack == 0);
+            need_walk = false;
+        }
+        // ---- one scan over the candidate list at the lanes' current H
+        double sf_d = mi, sd_d = 3.0 * mi;  // self: f(0) = 1, 3 f(0) + q f'(0) = 3
+        float sf_s = 0.f, sf_c = 0.f, sd_s = 0.f, sd_c = 0.f;
+        int cnt = 0;
+        const R Hr = (R)H;
+        const R Hinv = R(1) / Hr;
+        const double H2d = H * H;
+        const R H2 = MIXED ? Hr * Hr : (R)H2d;
+        bool first_chunk = true;
+        while (true) {
+            if (!first_chunk || !list_complete) {
+                // chunked walk: continue (or restart) the walk to refill the list
+                if (!first_chunk) {
+                    ws.ncand = 0;
+                    walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+                } else {
+                    walk_reset(stack, ws);
+                    walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+                }
+            }
+            for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
+                int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+                if (j >= 0) {
+                    if constexpr (MIXED) {
+                        double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
+                        if (per) {
+                            d0 = min_image(d0, g.L[0], g.halfL[0]);
+                            d1 = min_image(d1, g.L[1], g.halfL[1]);
+                            d2 = min_image(d2, g.L[2], g.halfL[2]);
+                        }
+                        tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
+                    } else {
+                        tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
+                    }
+                    tm[lane] = (R)a.ms[j];
+                } else {
+                    tx[lane] = (R)NAN; ty[lane] = 0; tz[lane] = 0; tm[lane] = 0;
+                }
+                cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
+                __syncthreads();
+                R pf = 0, pd = 0;
+#pragma unroll 4
+                for (int k = 0; k < kWave; ++k) {
+                    R r2;
+                    if constexpr (MIXED) {
+                        R dx = tx[k] - qx, dy = ty[k] - qy, dz = tz[k] - qz;
+                        r2 = dx * dx + dy * dy + dz * dz;
+                    } else {
+                        double dx = tx[k] - xi[0], dy = ty[k] - xi[1], dz = tz[k] - xi[2];
+                        if (per) {
+                            dx = min_image(dx, g.L[0], g.halfL[0]);
+                            dy = min_image(dy, g.L[1], g.halfL[1]);
+                            dz = min_image(dz, g.L[2], g.halfL[2]);
+                        }
+                        r2 = r2_exact(dx, dy, dz);
+                    }
+                    if (r2 < H2) {
+                        R q = sqrt(r2) * Hinv;
+                        R f, qfp;
+                        shape_f_qfp<K, R>(q, f, qfp);
+                        R mj = tm[k];
+                        pf += mj * f;
+                        pd += mj * (R(3) * f + qfp);
+                        ++cnt;
+                    }
+                }
+                if constexpr (MIXED) {
+                    neumaier(sf_s, sf_c, pf);
+                    neumaier(sd_s, sd_c, pd);
+                } else {
+                    sf_d += pf;
+                    sd_d += pd;
+                }
+                __syncthreads();
+            }
+            first_chunk = false;
+            if (ws.nstack == 0) break;  // walk finished
+        }
+        if constexpr (MIXED) {
+            sf_d += (double)sf_s + (double)sf_c;
+            sd_d += (double)sd_s + (double)sd_c;
+        }
+        ++scans;
+        // ---- Newton update per lane (bracketed, Sec. 2.3.3)
+        bool want_walk = false;
+        if (!done) {
+            const double H3 = H * H * H;
+            const double rh = sig * sf_d / H3;
+            const double drh = -sig * sd_d / (H3 * H);
+            const double omg = 1.0 + H * drh / (3.0 * rh);
+            const double F = c43 * H3 * rh - target;
+            const double dF = 4.0 * kPi * H * H * rh * omg;
+            rho = rh; om = omg; cnt_out = cnt;
+            if (F < 0.0) lo = H; else { hi = H; hi_ok = true; }
+            double Hn = dF > 0.0 ? H - F / dF : -1.0;
+            if (hi_ok) {
+                if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
+            } else {
+                if (H >= cap) { done = true; noconv = true; Hn = H; }
+                else {
+                    if (!(Hn > H)) Hn = 2.0 * H;
+                    if (Hn > cap) Hn = cap;
+                    if (Hn > Hw) {
+                        if (H < Hw) Hn = Hw;           // probe the search radius first
+                        else want_walk = true;         // root lies beyond the list
+                    }
+                }
+            }
+            if (!done) {
+                if (fabs(Hn - H) <= a.tol * H || F == 0.0) {
+                    done = true;
+                    if constexpr (MIXED) {
+                        // final Newton correction (FP32 sums resolve ~1e-7 only)
+                        rho = rh + drh * (Hn - H);
+                        H = Hn;
+                    }
+                } else {
+                    if (want_walk) Hw = fmin(cap, a.oversel * Hn);
+                    H = Hn;
+                }
+            }
+        }
+        if (__all(done)) break;
+        if (scans >= a.maxit) break;
+        if (__any(want_walk)) { need_walk = true; ++rewalks; }
+    }
+    if (act) {
+        if (!done) noconv = true;
+        a.Hs[i] = H;
+        a.rhos[i] = rho;
+        a.oms[i] = om;
+    }
+    // counters
+    int pairs = wave_sum_i(act ? cnt_out : 0);
+    int bad = wave_sum_i((act && noconv) ? 1 : 0);
+    int nact = wave_sum_i(act ? 1 : 0);
+    if (lane == 0) {
+        atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs);
+        atomicAdd(&a.cnt[C_CAND_D], cand_tested * (unsigned long long)nact);
+        atomicMax(&a.cnt[C_NR_ITER_MAX], (unsigned long long)scans);
+        atomicAdd(&a.cnt[C_NR_SCANS], (unsigned long long)scans);
+        if (bad) atomicAdd(&a.cnt[C_NOCONV], (unsigned long long)bad);
+        if (rewalks) atomicAdd(&a.cnt[C_REWALK], (unsigned long long)rewalks);
+        if (ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
+    }
+}
+
+// ================================================================ forces
+
+template <int K, bool MIXED>
+__global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
+    __shared__ uint32_t stack[kStackCap];
+    __shared__ uint32_t cand[kCandCap];
+    typedef typename std::conditional<MIXED, float, double>::type R;
+    __shared__ R tx[kWave], ty[kWave], tz[kWave], tvx[kWave], tvy[kWave], tvz[kWave];
+    __shared__ R tm[kWave], tH[kWave], tHi[kWave], tA[kWave], tc[kWave], trho[kWave];
+
+    const int lane = threadIdx.x;
+    const int64_t grp = blockIdx.x;
+    const int sid = a.grp_set[grp];
+    const SetGeom g = a.sets[sid];
+    const bool per = a.periodic != 0;
+    const double slop = set_slop(g);
+    const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
+    const bool act = i < g.p1;
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    const double Hd = act ? a.Hs[i] : 0.0;
+    const R sig = (R)sigma_of<K>();
+
+    double gc[3];
+    for (int q = 0; q < 3; ++q) {
+        double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
+        gc[q] = 0.5 * (mn + mx);
+    }
+    R qx = 0, qy = 0, qz = 0;
+    if constexpr (MIXED) {
+        qx = (R)(per ? min_image(xi[0] - gc[0], g.L[0], g.halfL[0]) : xi[0] - gc[0]);
+        qy = (R)(per ? min_image(xi[1] - gc[1], g.L[1], g.halfL[1]) : xi[1] - gc[1]);
+        qz = (R)(per ? min_image(xi[2] - gc[2], g.L[2], g.halfL[2]) : xi[2] - gc[2]);
+    }
+    const R Hi = (R)Hd;
+    const R Hiinv = act ? R(1) / Hi : R(0);
+    const R Hi2 = MIXED ? Hi * Hi : (R)(Hd * Hd);
+    const R Hi5inv = Hiinv * Hiinv * Hiinv * Hiinv * Hiinv;
+    const R vi[3] = {(R)(act ? a.vxs[i] : 0.0), (R)(act ? a.vys[i] : 0.0), (R)(act ? a.vzs[i] : 0.0)};
+    const R Ai = (R)(act ? a.As[i] : 0.0);
+    const R ci = (R)(act ? a.css[i] : 0.0);
+    const R rhoi = (R)(act ? a.rhos[i] : 1.0);
+    const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
+
+    Sink sk;
+    sink_bounds(act, xi, Hd, sk);
+    WalkState ws{0, 0, false};
+    walk_reset(stack, ws);
+
+    // accumulators: a (3), PdV sum, viscous heating sum
+    double acc_d[5] = {0, 0, 0, 0, 0};
+    float acc_s[5] = {0, 0, 0, 0, 0}, acc_c[5] = {0, 0, 0, 0, 0};
+    R mumax = 0;
+    int cnt = 0;
+    unsigned long long cand_tested = 0;
+
+    while (true) {
+        walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
+            int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+            if (j >= 0) {
+                if constexpr (MIXED) {
+                    double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
+                    if (per) {
+                        d0 = min_image(d0, g.L[0], g.halfL[0]);
+                        d1 = min_image(d1, g.L[1], g.halfL[1]);
+                        d2 = min_image(d2, g.L[2], g.halfL[2]);
+                    }
+                    tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
+                } else {
+                    tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
+                }
+                double Hj = a.Hs[j];
+                tvx[lane] = (R)a.vxs[j]; tvy[lane] = (R)a.vys[j]; tvz[lane] = (R)a.vzs[j];
+                tm[lane] = (R)a.ms[j];
+                tH[lane] = (R)Hj;
+                tHi[lane] = (R)(1.0 / Hj);
+                tA[lane] = (R)a.As[j];
+                tc[lane] = (R)a.css[j];
+                trho[lane] = (R)a.rhos[j];
+            } else {
+                tx[lane] = (R)NAN; ty[lane] = 0; tz[lane] = 0;
+                tvx[lane] = 0; tvy[lane] = 0; tvz[lane] = 0;
+                tm[lane] = 0; tH[lane] = 0; tHi[lane] = 0; tA[lane] = 0; tc[lane] = 0; trho[lane] = 1;
+            }
+            cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
+            __syncthreads();
+            R p[5] = {0, 0, 0, 0, 0};
+#pragma unroll 2
+            for (int k = 0; k < kWave; ++k) {
+                R dx, dy, dz, r2;
+                if constexpr (MIXED) {
+                    dx = tx[k] - qx; dy = ty[k] - qy; dz = tz[k] - qz;
+                    r2 = dx * dx + dy * dy + dz * dz;
+                } else {
+                    dx = tx[k] - xi[0]; dy = ty[k] - xi[1]; dz = tz[k] - xi[2];
+                    if (per) {
+                        dx = min_image(dx, g.L[0], g.halfL[0]);
+                        dy = min_image(dy, g.L[1], g.halfL[1]);
+                        dz = min_image(dz, g.L[2], g.halfL[2]);
+                    }
+                    r2 = r2_exact(dx, dy, dz);
+                }
+                const R Hj = tH[k];
+                const R Hj2 = Hj * Hj;
+                const R Hs2 = Hi2 > Hj2 ? Hi2 : Hj2;
+                if (r2 < Hs2) {
+                    ++cnt;
+                    const R r = sqrt(r2);
+                    R Gi = 0, Gj = 0;
+                    if (r2 < Hi2) {
+                        R q = r * Hiinv;
+                        Gi = sig * shape_g<K, R>(q, Hi, r) * Hi5inv;
+                    }
+                    if (r2 < Hj2) {
+                        const R hinv = tHi[k];
+                        R q = r * hinv;
+                        R h2 = hinv * hinv;
+                        Gj = sig * shape_g<K, R>(q, Hj, r) * (h2 * h2 * hinv);
+                    }
+                    // x_ij = x_i - x_j = -d ; v_ij = v_i - v_j
+                    const R xx = -dx, xy = -dy, xz = -dz;
+                    const R wx = vi[0] - tvx[k], wy = vi[1] - tvy[k], wz = vi[2] - tvz[k];
+                    const R vdotx = wx * xx + wy * xy + wz * xz;
+                    const R hbar = R(0.25) * (Hi + Hj);
+                    const R mu = hbar * vdotx / (r2 + eps * hbar * hbar);
+                    R Pi = 0;
+                    if (vdotx < R(0)) {
+                        const R cbar = R(0.5) * (ci + tc[k]);
+                        const R rbar = R(0.5) * (rhoi + trho[k]);
+                        Pi = (-alpha * cbar * mu + beta * mu * mu) / rbar;
+                    }
+                    const R Gbar = R(0.5) * (Gi + Gj);
+                    const R mj = tm[k];
+                    const R s = mj * (Ai * Gi + tA[k] * Gj + Pi * Gbar);
+                    p[0] -= s * xx;
+                    p[1] -= s * xy;
+                    p[2] -= s * xz;
+                    p[3] += mj * Gi * vdotx;
+                    p[4] += mj * Pi * Gbar * vdotx;
+                    mumax = -mu > mumax ? -mu : mumax;
+                }
+            }
+            for (int q = 0; q < 5; ++q) {
+                if constexpr (MIXED) neumaier(acc_s[q], acc_c[q], p[q]);
+                else acc_d[q] += p[q];
+            }
+            __syncthreads();
+        }
+        if (ws.nstack == 0) break;
+        ws.ncand = 0;
+    }
+    if constexpr (MIXED) {
+        for (int q = 0; q < 5; ++q) acc_d[q] = (double)acc_s[q] + (double)acc_c[q];
+    }
+    if (act) {
+        const double axv = acc_d[0], ayv = acc_d[1], azv = acc_d[2];
+        a.ax[i] = axv;
+        a.ay[i] = ayv;
+        a.az[i] = azv;
+        a.du[i] = (double)Ai * acc_d[3] + 0.5 * acc_d[4];
+        double amag = sqrt(axv * axv + ayv * ayv + azv * azv);
+        double dtv = a.dt_max;
+        if (amag > 0.0) dtv = fmin(dtv, a.eta_a * sqrt(Hd / amag));
+        double den = (1.0 + 0.6 * a.alpha) * (double)ci + 0.6 * a.beta * (double)mumax;
+        if (den > 0.0) dtv = fmin(dtv, a.eta_c * 0.5 * Hd / den);
+        a.dt[i] = dtv;
+    }
+    int pairs = wave_sum_i(act ? cnt : 0);
+    int nact = wave_sum_i(act ? 1 : 0);
+    if (lane == 0) {
+        atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs);
+        atomicAdd(&a.cnt[C_CAND_F], cand_tested * (unsigned long long)nact);
+        if (ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
+    }
+}
+
+// ================================================================ neighbour lists
+
+template <bool FORCE, bool FILL>
+__global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
+    __shared__ uint32_t stack[kStackCap];
+    __shared__ uint32_t cand[kCandCap];
+    __shared__ double tx[kWave], ty[kWave], tz[kWave], tH[kWave];
+    __shared__ int32_t tid[kWave];
+
+    const int lane = threadIdx.x;
+    const int64_t grp = blockIdx.x;
+    const int sid = a.grp_set[grp];
+    const SetGeom g = a.sets[sid];
+    const bool per = a.periodic != 0;
+    const double slop = set_slop(g);
+    const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
+    const bool act = i < g.p1;
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    const double Hd = act ? a.Hs[i] : 0.0;
+    const double Hi2 = Hd * Hd;
+    const int64_t orig = act ? (int64_t)a.perm[i] : 0;
+    int64_t wpos = (FILL && act) ? a.offsets[orig] : 0;
+
+    Sink sk;
+    sink_bounds(act, xi, Hd, sk);
+    WalkState ws{0, 0, false};
+    walk_reset(stack, ws);
+    int64_t cnt = 0;
+    while (true) {
+        walk<FORCE>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
+            int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+            tx[lane] = j >= 0 ? a.xs[j] : NAN;
+            ty[lane] = j >= 0 ? a.ys[j] : 0.0;
+            tz[lane] = j >= 0 ? a.zs[j] : 0.0;
+            tH[lane] = j >= 0 ? a.Hs[j] : 0.0;
+            tid[lane] = j >= 0 ? (int32_t)j : -1;
+            __syncthreads();
+            for (int k = 0; k < kWave; ++k) {
+                const int32_t jj = tid[k];
+                double dx = tx[k] - xi[0], dy = ty[k] - xi[1], dz = tz[k] - xi[2];
+                if (per) {
+                    dx = min_image(dx, g.L[0], g.halfL[0]);
+                    dy = min_image(dy, g.L[1], g.halfL[1]);
+                    dz = min_image(dz, g.L[2], g.halfL[2]);
+                }
+                double r2 = r2_exact(dx, dy, dz);
+                double Hs2 = Hi2;
+                if (FORCE) {
+                    double Hj2 = tH[k] * tH[k];
+                    Hs2 = Hs2 > Hj2 ? Hs2 : Hj2;
+                }
+                if (act && jj >= 0 && (int64_t)jj != i && r2 < Hs2) {
+                    if (FILL) a.idx[wpos + cnt] = (int32_t)a.perm[jj];
+                    ++cnt;
+                }
+            }
+            __syncthreads();
+        }
+        if (ws.nstack == 0) break;
+        ws.ncand = 0;
+    }
+    if (!FILL && act) a.row_count[orig] = cnt;
+    if (lane == 0 && ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
+}
+
+// One workgroup per row: bitonic sort in LDS (rows up to kMaxRow entries).
+__global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ offsets,
+                                                   int32_t *__restrict__ idx,
+                                                   unsigned long long *cnt) {
+    __shared__ int32_t v[kMaxRow];
+    const int64_t row = blockIdx.x;
+    const int64_t b = offsets[row], e = offsets[row + 1];
+    const int64_t len = e - b;
+    if (len <= 1) return;
+    if (len > kMaxRow) {
+        if (threadIdx.x == 0) atomicAdd(&cnt[C_ROWLONG], 1ull);
+        return;
+    }
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int t = threadIdx.x; t < P; t += blockDim.x) v[t] = t < len ? idx[b + t] : INT32_MAX;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = threadIdx.x; t < P; t += blockDim.x) {
+                int u = t ^ jj;
+                if (u > t) {
+                    bool up = (t & k) == 0;
+                    int32_t x = v[t], y = v[u];
+                    if ((x > y) == up) { v[t] = y; v[u] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < len; t += blockDim.x) idx[b + t] = v[t];
+}
+
+// ---------------------------------------------------------------- dispatch
+
+inline SweepArgs base_args(Ctx *c) {
+    SweepArgs a{};
+    a.sets = c->d_sets;
+    a.grp_set = c->d_grp_set;
+    a.nodes = c->nodes;
+    a.perm = c->d_perm[0];
+    a.xs = c->xs; a.ys = c->ys; a.zs = c->zs; a.ms = c->ms;
+    a.Hs = c->Hs; a.rhos = c->rhos; a.oms = c->oms;
+    a.vxs = c->vxs; a.vys = c->vys; a.vzs = c->vzs; a.As = c->As; a.css = c->css;
+    a.cnt = c->d_cnt;
+    a.B = c->bucket;
+    a.periodic = c->prm.periodic;
+    a.oversel = c->prm.oversel;
+    a.tol = c->prm.nr_tol;
+    a.h_max = c->prm.h_max;
+    a.n_ngb = c->prm.n_ngb;
+    a.maxit = c->prm.nr_maxit;
+    a.alpha = c->prm.alpha; a.beta = c->prm.beta; a.eps = c->prm.eps_av;
+    a.eta_a = c->prm.eta_a; a.eta_c = c->prm.eta_c; a.dt_max = c->prm.dt_max;
+    return a;
+}
+
+template <bool MIXED>
+hipError_t density_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
+    dim3 grid((unsigned)c->ngroups), block(kWave);
+    switch (c->prm.kernel) {
+    case 0: k_density<0, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 1: k_density<1, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 2: k_density<2, MIXED><<<grid, block, 0, s>>>(a); break;
+    default: k_density<3, MIXED><<<grid, block, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+template <bool MIXED>
+hipError_t forces_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
+    dim3 grid((unsigned)c->ngroups), block(kWave);
+    switch (c->prm.kernel) {
+    case 0: k_forces<0, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 1: k_forces<1, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 2: k_forces<2, MIXED><<<grid, block, 0, s>>>(a); break;
+    default: k_forces<3, MIXED><<<grid, block, 0, s>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_density(Ctx *c, hipStream_t s) {
+    if (c->ngroups == 0) return hipSuccess;
+    SweepArgs a = base_args(c);
+    return c->prm.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, a, s)
+                                              : density_dispatch<false>(c, a, s);
+}
+
+hipError_t launch_forces(Ctx *c, hipStream_t s) {
+    if (c->ngroups == 0) return hipSuccess;
+    SweepArgs a = base_args(c);
+    a.ax = c->axs; a.ay = c->ays; a.az = c->azs; a.du = c->dus; a.dt = c->dts;
+    return c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
+                                              : forces_dispatch<false>(c, a, s);
+}
+
+hipError_t launch_neighbors(Ctx *c, int mode, int64_t *row_count_caller, const int64_t *offsets,
+                            int32_t *idx, hipStream_t s) {
+    if (c->ngroups == 0) return hipSuccess;
+    SweepArgs a = base_args(c);
+    a.row_count = row_count_caller;
+    a.offsets = offsets;
+    a.idx = idx;
+    dim3 grid((unsigned)c->ngroups), block(kWave);
+    bool fill = idx != nullptr;
+    if (mode == SPH_MODE_FORCE) {
+        if (fill) k_neighbors<true, true><<<grid, block, 0, s>>>(a);
+        else k_neighbors<true, false><<<grid, block, 0, s>>>(a);
+    } else {
+        if (fill) k_neighbors<false, true><<<grid, block, 0, s>>>(a);
+        else k_neighbors<false, false><<<grid, block, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_rows(Ctx *c, const int64_t *offsets, int32_t *idx, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_sort_rows<<<(unsigned)c->n, 256, 0, s>>>(offsets, idx, c->d_cnt);
+    return hipGetLastError();
+}
+
+}  // namespace sphmi
