@@ -1,0 +1,192 @@
+"""Benchmark of the SPH neighbour-interaction sweep on one MI355X.
+
+Workload: 128^3 = 2 097 152 particles in the periodic unit cube, jittered cubic
+lattice, Wendland C4 kernel with 200 neighbours, ideal gas (the 2M-particle
+configuration the pair-rate metric is quoted on).  A timed step is one full
+sph_step: kick, drift, tree build, density with the smoothing-length
+iteration, EOS, forces, closing kick and FP64 reductions.
+
+value  = pair interactions per second of the whole step for the mixed path:
+         (sum_i |G_i| + sum_i |F_i|) counted by the kernels, divided by the
+         wall time of the timed steps (tree build and kick included).
+Also reported: the same for the FP64 path, the density+force-only rate of
+the metric's definition (kernel times from HIP events inside the library),
+the roofline of the dominant kernel and the FP64 CPU oracle on a sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--small]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Useful (algorithmic) floating-point operations per interaction, counted from
+# the formulas of the sweep for the Wendland C4 kernel (FMA counted as 2):
+#   density, per gather pair and smoothing-length iteration:
+#     x_j - x_i (3), r^2 (5), r (1), q (1), f(q) (10), q f'(q) (6), two sums (5) = 31
+#   force, per force-set pair:
+#     x_j - x_i (3), r^2 (5), r (1), two kernel gradients 2 x (q 1, g 8, G 2) = 22,
+#     v_ij (3), v.x (5), hbar (2), mu (6), viscosity Pi (10), Wbar gradient (2),
+#     pair scalar (6), acceleration (6), PdV and heating sums (7), signal speed (1) = 84
+FLOP_DENSITY_PAIR = 31
+FLOP_FORCE_PAIR = 84
+PEAK = {"f64": 78.6e12, "f32": 157.3e12}   # MI355X vector peaks (FP32 figure is the packed one)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(case, precision, steps, warmup):
+    import torch
+    import paper_2511_11425_amd as sph
+    p = dict(case["params"], precision=precision)
+    P = sph.ParticleArrays.from_state(case["state"], device="cuda:0")
+    ctx = sph.Context(p)
+    ctx.init(P)
+    for _ in range(warmup):
+        ctx.step(P)
+    torch.cuda.synchronize()
+    s0 = ctx.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.step(P)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = ctx.stats()
+    pairs = (s1["pairs_density_total"] - s0["pairs_density_total"]) + \
+            (s1["pairs_force_total"] - s0["pairs_force_total"])
+    wall = t1 - t0
+    # phase split with HIP events inside the library (separate, untimed above)
+    ctx.set_timing(True)
+    tden, tfor, ttree, ttot = [], [], [], []
+    for _ in range(max(3, min(steps, 10))):
+        ctx.step(P)
+        st = ctx.stats()
+        tden.append(st["t_density_ms"]); tfor.append(st["t_forces_ms"])
+        ttree.append(st["t_tree_ms"]); ttot.append(st["t_total_ms"])
+    ctx.set_timing(False)
+    st = ctx.stats()
+    res = {
+        "precision": precision,
+        "pairs_per_s": pairs / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "pairs_density": st["pairs_density"], "pairs_force": st["pairs_force"],
+        "cand_density": st["cand_density"], "cand_force": st["cand_force"],
+        "nr_scans_mean": st["nr_scans"] / max(1, (case["n"] + 63) // 64),
+        "nr_iter_max": st["nr_iter_max"], "n_noconv": st["n_noconv"],
+        "t_density_ms": float(np.median(tden)), "t_forces_ms": float(np.median(tfor)),
+        "t_tree_ms": float(np.median(ttree)), "t_step_ms": float(np.median(ttot)),
+    }
+    res["metric_rate"] = (st["pairs_density"] + st["pairs_force"]) / \
+        (1e-3 * (res["t_density_ms"] + res["t_forces_ms"]))
+    ctx.close()
+    del P
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(case, seconds=15.0):
+    """The FP64 oracle (as it stands) on a bounded sample of the same workload:
+    density (smoothing-length solve) and forces for a random subset of rows."""
+    import oracle
+    s, p = case["state"], case["params"]
+    n = len(s["x"])
+    rng = np.random.default_rng(123)
+    rows = np.sort(rng.choice(n, size=2000, replace=False))
+    t0 = time.perf_counter()
+    d = oracle.solve_h(p, s["x"], s["y"], s["z"], s["m"], s["H"], rows=rows)
+    t1 = time.perf_counter()
+    # full-size H/rho/Omega for the force sample: the oracle needs every particle's
+    # H; use the initial guess for the others (the force pass cost is the same)
+    H = s["H"].copy(); H[rows] = d["H"]
+    rho = np.full(n, 1.0); rho[rows] = d["rho"]
+    om = np.ones(n); om[rows] = d["omega"]
+    Pp, cs = oracle.eos(p, rho, s["u"])
+    t2 = time.perf_counter()
+    f = oracle.forces(p, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], H, rho, om,
+                      Pp, cs, rows=rows)
+    t3 = time.perf_counter()
+    pairs = int(d["count"].sum() + f["count"].sum())
+    secs = (t1 - t0) + (t3 - t2)
+    return {"value": pairs / secs, "unit": "pair interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{rows.size} random particles of the 128^3 Wendland C4 workload: smoothing-length "
+                      f"solve + forces, {pairs} pairs in {secs:.1f} s (grid build included)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--small", action="store_true", help="64^3 instead of 128^3 (quick check)")
+    ap.add_argument("--precisions", default="mixed,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import sph_inputs as si
+    n_side = 64 if args.small else 128
+    log(f"generating workload {n_side}^3")
+    case = si.config_large(n_side=n_side)
+    case["n"] = n_side ** 3
+    results = {}
+    for prec in args.precisions.split(","):
+        log(f"timing {prec}")
+        results[prec] = run_gpu(case, prec, args.steps, args.warmup)
+        log(json.dumps(results[prec]))
+    head = results.get("mixed") or results[next(iter(results))]
+    # roofline of the dominant kernel of the headline path
+    dom = "forces" if head["t_forces_ms"] >= head["t_density_ms"] else "density"
+    if dom == "forces":
+        flops = head["pairs_force"] * FLOP_FORCE_PAIR
+        t = head["t_forces_ms"] * 1e-3
+    else:
+        flops = head["pairs_density"] * FLOP_DENSITY_PAIR * head["nr_scans_mean"]
+        t = head["t_density_ms"] * 1e-3
+    dtype = "f32" if head["precision"] == "mixed" else "f64"
+    achieved = flops / t / 1e12
+    roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": PEAK[dtype] / 1e12,
+            "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK[dtype], "traffic": None}
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(case)
+    out = {
+        "metric": "pair interactions/sec (density+force) at 2M particles; FP32-mixed vs FP64",
+        "value": head["pairs_per_s"],
+        "unit": "pair interactions/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": f"{n_side}^3 jittered lattice, periodic unit cube, Wendland C4, "
+                               f"200 neighbours, full KDK step, mixed precision",
+                   "particles": n_side ** 3, "parallelism": "single GPU"},
+        "fp64": {k: results["fp64"][k] for k in ("pairs_per_s", "ms_per_step", "metric_rate")}
+        if "fp64" in results else None,
+        "mixed_vs_fp64": (results["mixed"]["pairs_per_s"] / results["fp64"]["pairs_per_s"])
+        if "mixed" in results and "fp64" in results else None,
+        "metric_rate_density_force_only": head["metric_rate"],
+        "phases_ms": {k: head[k] for k in ("t_tree_ms", "t_density_ms", "t_forces_ms", "t_step_ms")},
+        "pairs": {k: head[k] for k in ("pairs_density", "pairs_force", "cand_density",
+                                       "cand_force", "nr_scans_mean")},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

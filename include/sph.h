@@ -119,6 +119,12 @@ typedef struct {
     double e_kin, e_int;          /* sum m v^2/2, sum m u after the last step (FP64) */
     double dt_next;               /* min_i dt_i from the last force pass, capped by dt_max */
     double dt_used;               /* step size of the last sph_step */
+    int64_t pairs_density_total;  /* running sums of pairs_density / pairs_force over */
+    int64_t pairs_force_total;    /* every call since the context was created */
+    double t_tree_ms;             /* with sph_set_timing on: device time of the last call's */
+    double t_density_ms;          /* tree build, density kernel, force kernel and the whole */
+    double t_forces_ms;           /* call (HIP events on the call's stream); -1 when the */
+    double t_total_ms;            /* phase did not run or timing is off */
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -196,6 +202,10 @@ sph_status sph_graph_launch(sph_ctx *ctx, void *stream);
  * particles (synchronises; leaves H, rho, omega, P, c, a, dudt, dt written as
  * by sph_init).  The choice is kept in the context; returns it in *bucket. */
 sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *stream);
+
+/* Turns device-side phase timing on (1) or off (0); timings appear in sph_stats.
+ * Timing is skipped inside graph capture. */
+sph_status sph_set_timing(sph_ctx *ctx, int32_t enable);
 
 /* Synchronises the context's last stream and copies the counters. */
 sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out);

@@ -516,9 +516,13 @@ int orc_solve_h(const orc_params *p, int64_t n, const double *x, const double *y
                     double om = 1.0 + h * v.drho / (3.0 * v.rho);
                     double dF = 4.0 * ORC_PI * h * h * v.rho * om;
                     if (F < 0) lo = h; else hi = h;
-                    double hn = (dF > 0) ? h - F / dF : -1.0;
+                    /* stop on the size of the Newton step itself: near the root it
+                     * drops below the spacing of doubles, and h - step == h would
+                     * otherwise look like a step leaving the bracket */
+                    double step = (dF > 0) ? F / dF : NAN;
+                    if (F == 0.0 || fabs(step) <= tol * h) { Hc = h; break; }
+                    double hn = h - step;
                     if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-                    if (fabs(hn - h) <= tol * h || F == 0.0) { Hc = h; break; }
                     h = hn;
                     Hc = h;
                 }

@@ -31,7 +31,7 @@ MODE_GATHER, MODE_FORCE = 0, 1
 SYMBOLS = ("sph_default_params", "sph_version", "sph_last_error", "sph_create",
            "sph_create_batch", "sph_destroy", "sph_build_tree", "sph_neighbors", "sph_density",
            "sph_forces", "sph_init", "sph_step", "sph_graph_capture_step", "sph_graph_launch",
-           "sph_autotune", "sph_get_stats")
+           "sph_autotune", "sph_get_stats", "sph_set_timing")
 
 
 class Params(ctypes.Structure):
@@ -61,6 +61,9 @@ class Stats(ctypes.Structure):
         ("nr_scans", c_int64), ("n_noconv", c_int64), ("n_rewalk", c_int64),
         ("n_overflow", c_int64), ("momentum", c_double * 3), ("e_kin", c_double),
         ("e_int", c_double), ("dt_next", c_double), ("dt_used", c_double),
+        ("pairs_density_total", c_int64), ("pairs_force_total", c_int64),
+        ("t_tree_ms", c_double), ("t_density_ms", c_double), ("t_forces_ms", c_double),
+        ("t_total_ms", c_double),
     ]
 
 
@@ -85,9 +88,10 @@ _lib.sph_graph_capture_step.argtypes = [_ctx_p, POINTER(Particles), c_double, c_
 _lib.sph_graph_launch.argtypes = [_ctx_p, c_void_p]
 _lib.sph_autotune.argtypes = [_ctx_p, POINTER(Particles), POINTER(c_int32), c_void_p]
 _lib.sph_get_stats.argtypes = [_ctx_p, POINTER(Stats)]
+_lib.sph_set_timing.argtypes = [_ctx_p, c_int32]
 for _f in ("sph_create", "sph_create_batch", "sph_build_tree", "sph_neighbors", "sph_density",
            "sph_forces", "sph_init", "sph_step", "sph_graph_capture_step", "sph_graph_launch",
-           "sph_autotune", "sph_get_stats"):
+           "sph_autotune", "sph_get_stats", "sph_set_timing"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -250,6 +254,9 @@ class Context:
                                 _stream_ptr(stream))
         self._check(st)
         return offsets, idx[: int(need.value)]
+
+    def set_timing(self, on: bool = True):
+        self._check(_lib.sph_set_timing(self._h, 1 if on else 0))
 
     def stats(self) -> dict:
         s = Stats()

@@ -46,6 +46,11 @@ hipError_t dalloc(Ctx &c, T **p, size_t count) {
     return hipSuccess;
 }
 
+void free_events(Ctx &c) {
+    for (int e = 0; e < E_NEVENTS; ++e)
+        if (c.ev[e]) { (void)hipEventDestroy(c.ev[e]); c.ev[e] = nullptr; }
+}
+
 void free_all(Ctx &c) {
     if (c.graph_exec) { (void)hipGraphExecDestroy(c.graph_exec); c.graph_exec = nullptr; }
     if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
@@ -196,8 +201,9 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     return SPH_OK;
 }
 
-sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs) {
+sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs, int64_t n) {
     if (!p) return fail(x, SPH_ERR_INVALID, "particles is NULL");
+    if (n == 0) return SPH_OK;  // empty columns may be NULL
     if (!p->x || !p->y || !p->z || !p->vx || !p->vy || !p->vz || !p->m || !p->u || !p->H)
         return fail(x, SPH_ERR_INVALID, "a state array is NULL");
     if (outputs && (!p->rho || !p->omega || !p->P || !p->c || !p->ax || !p->ay || !p->az ||
@@ -207,7 +213,9 @@ sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs) {
 }
 
 hipError_t reset_counters(Ctx &c, hipStream_t s) {
-    return launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s);
+    c.ev_mask = 0;
+    mark(&c, E_BEGIN, s);
+    return launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s);
 }
 
 Cols cols0() {
@@ -276,6 +284,7 @@ sph_status do_step(sph_ctx *x, sph_particles *p, double dt, hipStream_t s) {
     if (st != SPH_OK) return st;
     HIPCHK(x, launch_closing_kick(&c, p, s), "closing kick");
     HIPCHK(x, launch_reduce(&c, p, s), "reduce");
+    mark(&c, E_END, s);
     return SPH_OK;
 }
 
@@ -353,6 +362,7 @@ void sph_destroy(sph_ctx *ctx) {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
     free_all(ctx->c);
+    free_events(ctx->c);
     delete ctx;
 }
 
@@ -360,7 +370,7 @@ sph_status sph_build_tree(sph_ctx *ctx, const sph_particles *p, int64_t n, void 
     if (!ctx) return SPH_ERR_INVALID;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
-    sph_status st = check_particles(ctx, p, false);
+    sph_status st = check_particles(ctx, p, false, n);
     if (st != SPH_OK) return st;
     if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(ctx, SPH_ERR_INVALID, "bad n");
     if (c.nsets == 1) {
@@ -416,11 +426,13 @@ sph_status sph_density(sph_ctx *ctx, sph_particles *p, void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
     if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
-    sph_status st = check_particles(ctx, p, true);
+    sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     c.last_stream = s;
     HIPCHK(ctx, reset_counters(c, s), "counters");
-    return do_density(ctx, p, s);
+    st = do_density(ctx, p, s);
+    mark(&c, E_END, s);
+    return st;
 }
 
 sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream) {
@@ -428,13 +440,14 @@ sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
     if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
-    sph_status st = check_particles(ctx, p, true);
+    sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     c.last_stream = s;
     HIPCHK(ctx, reset_counters(c, s), "counters");
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, true, s);
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
+    mark(&c, E_END, s);
     c.have_forces = true;
     return SPH_OK;
 }
@@ -443,16 +456,17 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     if (!ctx) return SPH_ERR_INVALID;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
-    sph_status st = check_particles(ctx, p, true);
+    sph_status st = check_particles(ctx, p, true, n);
     if (st != SPH_OK) return st;
     st = sph_build_tree(ctx, p, n, stream);
     if (st != SPH_OK) return st;
-    HIPCHK(ctx, reset_counters(c, s), "counters");
+    HIPCHK(ctx, launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s), "counters");
     st = do_density(ctx, p, s);
     if (st != SPH_OK) return st;
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, false, s);
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
+    mark(&c, E_END, s);
     c.have_forces = true;
     return SPH_OK;
 }
@@ -462,7 +476,7 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream) {
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
     if (!c.have_forces) return fail(ctx, SPH_ERR_STATE, "call sph_init before sph_step");
-    sph_status st = check_particles(ctx, p, true);
+    sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     if (!(dt == dt)) return fail(ctx, SPH_ERR_INVALID, "dt is NaN");
     c.last_stream = s;
@@ -474,13 +488,15 @@ sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, voi
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
     if (!c.have_forces) return fail(ctx, SPH_ERR_STATE, "call sph_init before capturing a step");
-    sph_status st = check_particles(ctx, p, true);
+    sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     if (!s) return fail(ctx, SPH_ERR_INVALID, "graph capture needs a non-null stream");
     if (c.graph_exec) { (void)hipGraphExecDestroy(c.graph_exec); c.graph_exec = nullptr; }
     if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
     HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    c.capturing = true;
     st = do_step(ctx, p, dt, s);
+    c.capturing = false;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st != SPH_OK) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -524,6 +540,30 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->e_int = c.h_rep->e_int;
     out->dt_next = c.h_rep->dt_next;
     out->dt_used = c.h_rep->dt_used;
+    out->pairs_density_total = (int64_t)c.h_cnt[C_PAIRS_D_TOT];
+    out->pairs_force_total = (int64_t)c.h_cnt[C_PAIRS_F_TOT];
+    auto span = [&](int a, int b) -> double {
+        if (!((c.ev_mask >> a) & 1u) || !((c.ev_mask >> b) & 1u)) return -1.0;
+        float ms = -1.0f;
+        if (hipEventElapsedTime(&ms, c.ev[a], c.ev[b]) != hipSuccess) return -1.0;
+        return (double)ms;
+    };
+    out->t_tree_ms = span(E_TREE0, E_TREE1);
+    out->t_density_ms = span(E_DEN0, E_DEN1);
+    out->t_forces_ms = span(E_FOR0, E_FOR1);
+    out->t_total_ms = span(E_BEGIN, E_END);
+    return SPH_OK;
+}
+
+sph_status sph_set_timing(sph_ctx *ctx, int32_t enable) {
+    if (!ctx) return SPH_ERR_INVALID;
+    Ctx &c = ctx->c;
+    if (enable && !c.ev[0]) {
+        for (int e = 0; e < E_NEVENTS; ++e)
+            HIPCHK(ctx, hipEventCreate(&c.ev[e]), "event create");
+    }
+    c.timing = enable != 0;
+    c.ev_mask = 0;
     return SPH_OK;
 }
 

@@ -23,8 +23,15 @@ constexpr int kMaxRow = 4096;      // longest neighbour row sph_neighbors can so
 // atomics so totals do not depend on scheduling).
 enum Counter {
     C_PAIRS_D = 0, C_PAIRS_F, C_CAND_D, C_CAND_F, C_NR_ITER_MAX, C_NR_SCANS,
-    C_NOCONV, C_REWALK, C_OVERFLOW, C_ROWLONG, C_NCOUNTERS
+    C_NOCONV, C_REWALK, C_OVERFLOW, C_ROWLONG,
+    C_NTRANSIENT,                         // counters above are cleared by every call
+    C_PAIRS_D_TOT = C_NTRANSIENT,         // running totals since the context was made
+    C_PAIRS_F_TOT,
+    C_NCOUNTERS
 };
+
+// Timing events recorded around the phases when timing is on.
+enum TimingEvent { E_BEGIN = 0, E_TREE0, E_TREE1, E_DEN0, E_DEN1, E_FOR0, E_FOR1, E_END, E_NEVENTS };
 
 // FP64 results of the last step (device), copied into sph_stats.
 struct StepReport {
@@ -114,6 +121,12 @@ struct Ctx {
     unsigned long long *h_cnt = nullptr; // pinned host mirrors
     StepReport *h_rep = nullptr;
 
+    // phase timing (hipEvents on the call's stream; off during graph capture)
+    bool timing = false;
+    bool capturing = false;
+    hipEvent_t ev[E_NEVENTS] = {};
+    unsigned ev_mask = 0;           // events recorded by the last call
+
     // graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -155,5 +168,12 @@ hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s);
 hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s);
 hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s);
 int reduce_partials();
+
+// Records timing event e on stream s when timing is on (no-op otherwise).
+inline void mark(Ctx *c, int e, hipStream_t s) {
+    if (c->timing && !c->capturing && c->ev[e]) {
+        if (hipEventRecord(c->ev[e], s) == hipSuccess) c->ev_mask |= 1u << e;
+    }
+}
 
 }  // namespace sphmi

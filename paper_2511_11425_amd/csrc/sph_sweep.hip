@@ -355,7 +355,9 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
             need_walk = false;
         }
         // ---- one scan over the candidate list at the lanes' current H
-        double sf_d = mi, sd_d = 3.0 * mi;  // self: f(0) = 1, 3 f(0) + q f'(0) = 3
+        // the particle meets itself in the candidate list (r = 0: f = 1, q f' = 0),
+        // which is the self term of the density; it is not counted as a neighbour
+        double sf_d = 0.0, sd_d = 0.0;
         float sf_s = 0.f, sf_c = 0.f, sd_s = 0.f, sd_c = 0.f;
         int cnt = 0;
         const R Hr = (R)H;
@@ -446,14 +448,27 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
             const double omg = 1.0 + H * drh / (3.0 * rh);
             const double F = c43 * H3 * rh - target;
             const double dF = 4.0 * kPi * H * H * rh * omg;
-            rho = rh; om = omg; cnt_out = cnt;
+            rho = rh; om = omg; cnt_out = cnt - 1;
             if (F < 0.0) lo = H; else { hi = H; hi_ok = true; }
-            double Hn = dF > 0.0 ? H - F / dF : -1.0;
-            if (hi_ok) {
-                if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
+            // Newton step; the stopping test looks at the step before the
+            // bracket safeguard (a step below the spacing of doubles leaves
+            // H - step == H, which must not read as leaving the bracket)
+            const double step = dF > 0.0 ? F / dF : NAN;
+            if (F == 0.0 || fabs(step) <= a.tol * H) {
+                done = true;
+                if constexpr (MIXED) {
+                    // take the final Newton correction too (FP32 sums resolve ~1e-7)
+                    rho = rh - drh * step;
+                    H = H - step;
+                }
+            } else if (F < 0.0 && H >= cap) {
+                done = true;   // the root lies beyond the cap
+                noconv = true;
             } else {
-                if (H >= cap) { done = true; noconv = true; Hn = H; }
-                else {
+                double Hn = H - step;
+                if (hi_ok) {
+                    if (!(Hn > lo && Hn < hi)) Hn = 0.5 * (lo + hi);
+                } else {
                     if (!(Hn > H)) Hn = 2.0 * H;
                     if (Hn > cap) Hn = cap;
                     if (Hn > Hw) {
@@ -461,19 +476,8 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                         else want_walk = true;         // root lies beyond the list
                     }
                 }
-            }
-            if (!done) {
-                if (fabs(Hn - H) <= a.tol * H || F == 0.0) {
-                    done = true;
-                    if constexpr (MIXED) {
-                        // final Newton correction (FP32 sums resolve ~1e-7 only)
-                        rho = rh + drh * (Hn - H);
-                        H = Hn;
-                    }
-                } else {
-                    if (want_walk) Hw = fmin(cap, a.oversel * Hn);
-                    H = Hn;
-                }
+                if (want_walk) Hw = fmin(cap, a.oversel * Hn);
+                H = Hn;
             }
         }
         if (__all(done)) break;
@@ -492,6 +496,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     int nact = wave_sum_i(act ? 1 : 0);
     if (lane == 0) {
         atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs);
+        atomicAdd(&a.cnt[C_PAIRS_D_TOT], (unsigned long long)pairs);
         atomicAdd(&a.cnt[C_CAND_D], cand_tested * (unsigned long long)nact);
         atomicMax(&a.cnt[C_NR_ITER_MAX], (unsigned long long)scans);
         atomicAdd(&a.cnt[C_NR_SCANS], (unsigned long long)scans);
@@ -606,8 +611,10 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                 const R Hj = tH[k];
                 const R Hj2 = Hj * Hj;
                 const R Hs2 = Hi2 > Hj2 ? Hi2 : Hj2;
-                if (r2 < Hs2) {
-                    ++cnt;
+                if (r2 < Hs2) ++cnt;
+                // a pair at r = 0 (the particle itself, or a coincident one) exerts
+                // no force and no heating: x_ij = 0 and v_ij . x_ij = 0
+                if (r2 < Hs2 && r2 > R(0)) {
                     const R r = sqrt(r2);
                     R Gi = 0, Gj = 0;
                     if (r2 < Hi2) {
@@ -668,10 +675,12 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
         if (den > 0.0) dtv = fmin(dtv, a.eta_c * 0.5 * Hd / den);
         a.dt[i] = dtv;
     }
-    int pairs = wave_sum_i(act ? cnt : 0);
+    // the particle itself passed the distance test once (r = 0, no force)
+    int pairs = wave_sum_i(act ? cnt - 1 : 0);
     int nact = wave_sum_i(act ? 1 : 0);
     if (lane == 0) {
         atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs);
+        atomicAdd(&a.cnt[C_PAIRS_F_TOT], (unsigned long long)pairs);
         atomicAdd(&a.cnt[C_CAND_F], cand_tested * (unsigned long long)nact);
         if (ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
     }
@@ -829,16 +838,22 @@ hipError_t forces_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
 hipError_t launch_density(Ctx *c, hipStream_t s) {
     if (c->ngroups == 0) return hipSuccess;
     SweepArgs a = base_args(c);
-    return c->prm.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, a, s)
-                                              : density_dispatch<false>(c, a, s);
+    mark(c, E_DEN0, s);
+    hipError_t e = c->prm.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, a, s)
+                                                      : density_dispatch<false>(c, a, s);
+    mark(c, E_DEN1, s);
+    return e;
 }
 
 hipError_t launch_forces(Ctx *c, hipStream_t s) {
     if (c->ngroups == 0) return hipSuccess;
     SweepArgs a = base_args(c);
     a.ax = c->axs; a.ay = c->ays; a.az = c->azs; a.du = c->dus; a.dt = c->dts;
-    return c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
-                                              : forces_dispatch<false>(c, a, s);
+    mark(c, E_FOR0, s);
+    hipError_t e = c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
+                                                      : forces_dispatch<false>(c, a, s);
+    mark(c, E_FOR1, s);
+    return e;
 }
 
 hipError_t launch_neighbors(Ctx *c, int mode, int64_t *row_count_caller, const int64_t *offsets,

@@ -391,6 +391,7 @@ hipError_t launch_init_nodes(Ctx *c, hipStream_t s) {
 }
 
 hipError_t launch_refit(Ctx *c, hipStream_t s) {
+    if (c->nbuckets == 0) return hipSuccess;
     k_leaf_bounds<<<nblk(c->nbuckets, 128), 128, 0, s>>>(c->d_sets, c->d_bkt_set, c->nbuckets,
                                                          c->bucket, c->xs, c->ys, c->zs, c->Hs,
                                                          c->nodes, c->bref, c->fxs, c->fys, c->fzs);
@@ -406,6 +407,7 @@ hipError_t launch_refit(Ctx *c, hipStream_t s) {
 
 hipError_t launch_tree_build(Ctx *c, const sph_particles *p, hipStream_t s) {
     const int64_t n = c->n;
+    mark(c, E_TREE0, s);
     if (!c->prm.periodic) {
         long long *enc = reinterpret_cast<long long *>(c->d_bbox);
         k_bbox_init<<<nblk(6 * c->nsets, 256), 256, 0, s>>>(enc, c->nsets);
@@ -437,7 +439,9 @@ hipError_t launch_tree_build(Ctx *c, const sph_particles *p, hipStream_t s) {
                                           c->ys, c->zs, c->ms, c->Hs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_refit(c, s);
+    e = launch_refit(c, s);
+    mark(c, E_TREE1, s);
+    return e;
 }
 
 }  // namespace sphmi
