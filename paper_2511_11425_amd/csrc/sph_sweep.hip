@@ -239,6 +239,20 @@ __device__ void walk(const SetGeom &g, bool per, double slop, const Node *__rest
     }
 }
 
+__device__ __forceinline__ float wrap_f(float d, float L, float hL) {
+    if (d > hL) return d - L;
+    if (d < -hL) return d + L;
+    return d;
+}
+
+__device__ __forceinline__ bool group_needs_wrap(bool per, const SetGeom &g, const double *gext,
+                                                 double reach) {
+    if (!per) return false;
+    for (int a = 0; a < 3; ++a)
+        if (gext[a] + reach >= 0.5 * g.L[a] * (1.0 - 1e-6)) return true;
+    return false;
+}
+
 // Neumaier-compensated accumulation (FP32 partial sums of the mixed path).
 __device__ __forceinline__ void neumaier(float &sum, float &comp, float v) {
     float t = sum + v;
@@ -291,14 +305,86 @@ __device__ __forceinline__ int64_t slot_index(const SetGeom &g, const uint32_t *
     return j < g.p1 ? j : -1;
 }
 
+// ================================================================ pair compaction
+//
+// A staged tile holds 64 candidates; a wave holds 64 sinks.  Evaluating the
+// full 64 x 64 block with one sink per lane executes the interaction maths for
+// every candidate that ANY lane accepts, i.e. for nearly all of them, while
+// only ~15% of the (sink, candidate) pairs are neighbours.  The sweep
+// therefore runs two phases per tile:
+//   test     lane = sink, candidates by LDS broadcast, distance test only;
+//            the accepted pairs of each candidate are ballot-compacted into an
+//            LDS pair list, candidate-major (so consecutive entries rarely
+//            share a sink);
+//   interact lane = pair: 64 accepted pairs per step, contributions added to
+//            the sink's LDS accumulator with LDS float atomics (one wave per
+//            workgroup, so the order of the adds is fixed).
+// Each sink then folds the tile's partial sums into its own accumulators.
+
+template <class Hit>
+__device__ __forceinline__ int compact_tile(uint16_t *pairs, Hit hit, int &hits) {
+    const int lane = threadIdx.x;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int base = 0;
+#pragma unroll 8
+    for (int k = 0; k < kWave; ++k) {
+        const bool h = hit(k);
+        const uint64_t bal = __ballot(h);
+        if (h) pairs[base + __popcll(bal & lt)] = (uint16_t)((lane << 6) | k);
+        hits += h ? 1 : 0;
+        base += __popcll(bal);
+    }
+    return base;
+}
+
+template <class Pair>
+__device__ __forceinline__ void for_pairs(const uint16_t *pairs, int T, Pair f) {
+    for (int c = 0; c < T; c += kWave) {
+        const int t = c + (int)threadIdx.x;
+        if (t < T) {
+            const uint16_t p = pairs[t];
+            f((int)(p >> 6), (int)(p & 63));
+        }
+    }
+}
+
+// Pair difference d = x_k - x_i (candidate minus sink).  FP64: absolute
+// coordinates, minimum image, distance without contraction.  Mixed: FP32
+// coordinates relative to the group centre, re-wrapped only when the group is
+// too wide for the single image chosen at staging.
+template <bool MIXED, bool WRAP, typename R>
+__device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool per,
+                                     const SetGeom &g, const R *Lf, const R *hLf,
+                                     R &dx, R &dy, R &dz) {
+    dx = xk - xi; dy = yk - yi; dz = zk - zi;
+    if constexpr (MIXED) {
+        if constexpr (WRAP) {
+            dx = wrap_f(dx, Lf[0], hLf[0]);
+            dy = wrap_f(dy, Lf[1], hLf[1]);
+            dz = wrap_f(dz, Lf[2], hLf[2]);
+        }
+        return dx * dx + dy * dy + dz * dz;
+    } else {
+        if (per) {
+            dx = min_image(dx, g.L[0], g.halfL[0]);
+            dy = min_image(dy, g.L[1], g.halfL[1]);
+            dz = min_image(dz, g.L[2], g.halfL[2]);
+        }
+        return r2_exact(dx, dy, dz);
+    }
+}
+
 // ================================================================ density
 
 template <int K, bool MIXED>
 __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
+    typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
-    typedef typename std::conditional<MIXED, float, double>::type R;
+    __shared__ uint16_t pairs[kWave * kWave];
     __shared__ R tx[kWave], ty[kWave], tz[kWave], tm[kWave];
+    __shared__ R sx[kWave], sy[kWave], sz[kWave], sHinv[kWave];
+    __shared__ R accf[kWave], accd[kWave];
 
     const int lane = threadIdx.x;
     const int64_t grp = blockIdx.x;
@@ -326,18 +412,27 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     double rho = 0.0, om = 1.0;
     int cnt_out = 0;
 
-    // group reference point for the mixed path (cell centre of the group)
+    // group centre (reference point of the mixed path's FP32 coordinates)
     double gc[3];
     for (int q = 0; q < 3; ++q) {
         double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
         gc[q] = 0.5 * (mn + mx);
     }
-    R qx = 0, qy = 0, qz = 0;
+    double gext[3];
+    for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
+    const R Lf[3] = {(R)g.L[0], (R)g.L[1], (R)g.L[2]};
+    const R hLf[3] = {(R)g.halfL[0], (R)g.halfL[1], (R)g.halfL[2]};
+    R qx, qy, qz;
     if constexpr (MIXED) {
         qx = (R)(per ? min_image(xi[0] - gc[0], g.L[0], g.halfL[0]) : xi[0] - gc[0]);
         qy = (R)(per ? min_image(xi[1] - gc[1], g.L[1], g.halfL[1]) : xi[1] - gc[1]);
         qz = (R)(per ? min_image(xi[2] - gc[2], g.L[2], g.halfL[2]) : xi[2] - gc[2]);
+    } else {
+        qx = xi[0]; qy = xi[1]; qz = xi[2];
     }
+    sx[lane] = qx; sy[lane] = qy; sz[lane] = qz;
+    accf[lane] = 0; accd[lane] = 0;
+    bool wrapf = false;
 
     WalkState ws{0, 0, false};
     Sink sk;
@@ -353,21 +448,21 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
             walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
             list_complete = (ws.nstack == 0);
             need_walk = false;
+            if constexpr (MIXED) wrapf = group_needs_wrap(per, g, gext, wave_max(act ? Hw : 0.0));
         }
-        // ---- one scan over the candidate list at the lanes' current H
-        // the particle meets itself in the candidate list (r = 0: f = 1, q f' = 0),
-        // which is the self term of the density; it is not counted as a neighbour
+        // ---- one scan over the candidate list at the lanes' current H.  The
+        // particle meets itself (r = 0: f = 1, q f' = 0), which is the self
+        // term of the density; it is not counted as a neighbour.
         double sf_d = 0.0, sd_d = 0.0;
         float sf_s = 0.f, sf_c = 0.f, sd_s = 0.f, sd_c = 0.f;
         int cnt = 0;
         const R Hr = (R)H;
         const R Hinv = R(1) / Hr;
-        const double H2d = H * H;
-        const R H2 = MIXED ? Hr * Hr : (R)H2d;
+        const R H2 = MIXED ? Hr * Hr : (R)(H * H);
+        sHinv[lane] = Hinv;
         bool first_chunk = true;
         while (true) {
             if (!first_chunk || !list_complete) {
-                // chunked walk: continue (or restart) the walk to refill the list
                 if (!first_chunk) {
                     ws.ncand = 0;
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
@@ -396,32 +491,31 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                 }
                 cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
                 __syncthreads();
-                R pf = 0, pd = 0;
-#pragma unroll 4
-                for (int k = 0; k < kWave; ++k) {
-                    R r2;
-                    if constexpr (MIXED) {
-                        R dx = tx[k] - qx, dy = ty[k] - qy, dz = tz[k] - qz;
-                        r2 = dx * dx + dy * dy + dz * dz;
-                    } else {
-                        double dx = tx[k] - xi[0], dy = ty[k] - xi[1], dz = tz[k] - xi[2];
-                        if (per) {
-                            dx = min_image(dx, g.L[0], g.halfL[0]);
-                            dy = min_image(dy, g.L[1], g.halfL[1]);
-                            dz = min_image(dz, g.L[2], g.halfL[2]);
-                        }
-                        r2 = r2_exact(dx, dy, dz);
-                    }
-                    if (r2 < H2) {
-                        R q = sqrt(r2) * Hinv;
+                auto tile = [&](auto wrap_tag) {
+                    constexpr bool WRAP = decltype(wrap_tag)::value;
+                    R dx, dy, dz;
+                    const int T = compact_tile(pairs, [&](int k) {
+                        return pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], qx, qy, qz, per, g,
+                                                       Lf, hLf, dx, dy, dz) < H2;
+                    }, cnt);
+                    __syncthreads();
+                    for_pairs(pairs, T, [&](int s, int k) {
+                        R ex, ey, ez;
+                        const R r2 = pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], sx[s], sy[s],
+                                                             sz[s], per, g, Lf, hLf, ex, ey, ez);
+                        R q = sqrt(r2) * sHinv[s];
                         R f, qfp;
                         shape_f_qfp<K, R>(q, f, qfp);
-                        R mj = tm[k];
-                        pf += mj * f;
-                        pd += mj * (R(3) * f + qfp);
-                        ++cnt;
-                    }
-                }
+                        const R mj = tm[k];
+                        atomicAdd(&accf[s], mj * f);
+                        atomicAdd(&accd[s], mj * (R(3) * f + qfp));
+                    });
+                };
+                if (MIXED && wrapf) tile(std::true_type{});
+                else tile(std::false_type{});
+                __syncthreads();
+                const R pf = accf[lane], pd = accd[lane];
+                accf[lane] = 0; accd[lane] = 0;
                 if constexpr (MIXED) {
                     neumaier(sf_s, sf_c, pf);
                     neumaier(sd_s, sd_c, pd);
@@ -429,7 +523,6 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                     sf_d += pf;
                     sd_d += pd;
                 }
-                __syncthreads();
             }
             first_chunk = false;
             if (ws.nstack == 0) break;  // walk finished
@@ -491,12 +584,12 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
         a.oms[i] = om;
     }
     // counters
-    int pairs = wave_sum_i(act ? cnt_out : 0);
+    int pairs_n = wave_sum_i(act ? cnt_out : 0);
     int bad = wave_sum_i((act && noconv) ? 1 : 0);
     int nact = wave_sum_i(act ? 1 : 0);
     if (lane == 0) {
-        atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs);
-        atomicAdd(&a.cnt[C_PAIRS_D_TOT], (unsigned long long)pairs);
+        atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs_n);
+        atomicAdd(&a.cnt[C_PAIRS_D_TOT], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_CAND_D], cand_tested * (unsigned long long)nact);
         atomicMax(&a.cnt[C_NR_ITER_MAX], (unsigned long long)scans);
         atomicAdd(&a.cnt[C_NR_SCANS], (unsigned long long)scans);
@@ -510,11 +603,16 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
 
 template <int K, bool MIXED>
 __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
+    typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
-    typedef typename std::conditional<MIXED, float, double>::type R;
+    __shared__ uint16_t pairs[kWave * kWave];
     __shared__ R tx[kWave], ty[kWave], tz[kWave], tvx[kWave], tvy[kWave], tvz[kWave];
     __shared__ R tm[kWave], tH[kWave], tHi[kWave], tA[kWave], tc[kWave], trho[kWave];
+    __shared__ R sx[kWave], sy[kWave], sz[kWave], svx[kWave], svy[kWave], svz[kWave];
+    __shared__ R sH[kWave], sHi[kWave], sA[kWave], sc[kWave], srho[kWave];
+    __shared__ R acc[5][kWave];
+    __shared__ R amu[kWave];
 
     const int lane = threadIdx.x;
     const int64_t grp = blockIdx.x;
@@ -533,20 +631,35 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
         double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
         gc[q] = 0.5 * (mn + mx);
     }
-    R qx = 0, qy = 0, qz = 0;
+    double gext[3];
+    for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
+    const R Lf[3] = {(R)g.L[0], (R)g.L[1], (R)g.L[2]};
+    const R hLf[3] = {(R)g.halfL[0], (R)g.halfL[1], (R)g.halfL[2]};
+    const double Hsink_max = wave_max(act ? Hd : 0.0);
+    R qx, qy, qz;
     if constexpr (MIXED) {
         qx = (R)(per ? min_image(xi[0] - gc[0], g.L[0], g.halfL[0]) : xi[0] - gc[0]);
         qy = (R)(per ? min_image(xi[1] - gc[1], g.L[1], g.halfL[1]) : xi[1] - gc[1]);
         qz = (R)(per ? min_image(xi[2] - gc[2], g.L[2], g.halfL[2]) : xi[2] - gc[2]);
+    } else {
+        qx = xi[0]; qy = xi[1]; qz = xi[2];
     }
     const R Hi = (R)Hd;
-    const R Hiinv = act ? R(1) / Hi : R(0);
     const R Hi2 = MIXED ? Hi * Hi : (R)(Hd * Hd);
-    const R Hi5inv = Hiinv * Hiinv * Hiinv * Hiinv * Hiinv;
-    const R vi[3] = {(R)(act ? a.vxs[i] : 0.0), (R)(act ? a.vys[i] : 0.0), (R)(act ? a.vzs[i] : 0.0)};
     const R Ai = (R)(act ? a.As[i] : 0.0);
     const R ci = (R)(act ? a.css[i] : 0.0);
-    const R rhoi = (R)(act ? a.rhos[i] : 1.0);
+    // sink data for the interaction phase
+    sx[lane] = qx; sy[lane] = qy; sz[lane] = qz;
+    svx[lane] = (R)(act ? a.vxs[i] : 0.0);
+    svy[lane] = (R)(act ? a.vys[i] : 0.0);
+    svz[lane] = (R)(act ? a.vzs[i] : 0.0);
+    sH[lane] = Hi;
+    sHi[lane] = act ? R(1) / Hi : R(0);
+    sA[lane] = Ai;
+    sc[lane] = ci;
+    srho[lane] = (R)(act ? a.rhos[i] : 1.0);
+    for (int q = 0; q < 5; ++q) acc[q][lane] = 0;
+    amu[lane] = 0;
     const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
 
     Sink sk;
@@ -554,10 +667,8 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
     WalkState ws{0, 0, false};
     walk_reset(stack, ws);
 
-    // accumulators: a (3), PdV sum, viscous heating sum
     double acc_d[5] = {0, 0, 0, 0, 0};
     float acc_s[5] = {0, 0, 0, 0, 0}, acc_c[5] = {0, 0, 0, 0, 0};
-    R mumax = 0;
     int cnt = 0;
     unsigned long long cand_tested = 0;
 
@@ -591,74 +702,83 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                 tm[lane] = 0; tH[lane] = 0; tHi[lane] = 0; tA[lane] = 0; tc[lane] = 0; trho[lane] = 1;
             }
             cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
+            bool wrapf = false;
+            if constexpr (MIXED) {
+                double reach = fmax(Hsink_max, wave_max(j >= 0 ? a.Hs[j] : 0.0));
+                wrapf = group_needs_wrap(per, g, gext, reach);
+            }
             __syncthreads();
-            R p[5] = {0, 0, 0, 0, 0};
-#pragma unroll 2
-            for (int k = 0; k < kWave; ++k) {
-                R dx, dy, dz, r2;
-                if constexpr (MIXED) {
-                    dx = tx[k] - qx; dy = ty[k] - qy; dz = tz[k] - qz;
-                    r2 = dx * dx + dy * dy + dz * dz;
-                } else {
-                    dx = tx[k] - xi[0]; dy = ty[k] - xi[1]; dz = tz[k] - xi[2];
-                    if (per) {
-                        dx = min_image(dx, g.L[0], g.halfL[0]);
-                        dy = min_image(dy, g.L[1], g.halfL[1]);
-                        dz = min_image(dz, g.L[2], g.halfL[2]);
-                    }
-                    r2 = r2_exact(dx, dy, dz);
-                }
-                const R Hj = tH[k];
-                const R Hj2 = Hj * Hj;
-                const R Hs2 = Hi2 > Hj2 ? Hi2 : Hj2;
-                if (r2 < Hs2) ++cnt;
-                // a pair at r = 0 (the particle itself, or a coincident one) exerts
-                // no force and no heating: x_ij = 0 and v_ij . x_ij = 0
-                if (r2 < Hs2 && r2 > R(0)) {
+            auto tile = [&](auto wrap_tag) {
+                constexpr bool WRAP = decltype(wrap_tag)::value;
+                R dx, dy, dz;
+                // r = 0 pairs (the particle itself, or a coincident one) count as
+                // neighbours but exert no force and no heating (x_ij = 0)
+                int interacting = 0;
+                const int T = compact_tile(pairs, [&](int k) {
+                    const R r2 = pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], qx, qy, qz, per, g,
+                                                         Lf, hLf, dx, dy, dz);
+                    const R Hj = tH[k];
+                    const R Hj2 = Hj * Hj;
+                    const bool in = r2 < (Hi2 > Hj2 ? Hi2 : Hj2);
+                    cnt += in ? 1 : 0;
+                    return in && r2 > R(0);
+                }, interacting);
+                __syncthreads();
+                for_pairs(pairs, T, [&](int s, int k) {
+                    R ex, ey, ez;
+                    const R r2 = pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], sx[s], sy[s], sz[s],
+                                                         per, g, Lf, hLf, ex, ey, ez);
                     const R r = sqrt(r2);
+                    const R Hs_ = sH[s], Hj = tH[k];
                     R Gi = 0, Gj = 0;
-                    if (r2 < Hi2) {
-                        R q = r * Hiinv;
-                        Gi = sig * shape_g<K, R>(q, Hi, r) * Hi5inv;
+                    if (r2 < Hs_ * Hs_) {
+                        const R hinv = sHi[s];
+                        const R h2 = hinv * hinv;
+                        Gi = sig * shape_g<K, R>(r * hinv, Hs_, r) * (h2 * h2 * hinv);
                     }
-                    if (r2 < Hj2) {
+                    if (r2 < Hj * Hj) {
                         const R hinv = tHi[k];
-                        R q = r * hinv;
-                        R h2 = hinv * hinv;
-                        Gj = sig * shape_g<K, R>(q, Hj, r) * (h2 * h2 * hinv);
+                        const R h2 = hinv * hinv;
+                        Gj = sig * shape_g<K, R>(r * hinv, Hj, r) * (h2 * h2 * hinv);
                     }
                     // x_ij = x_i - x_j = -d ; v_ij = v_i - v_j
-                    const R xx = -dx, xy = -dy, xz = -dz;
-                    const R wx = vi[0] - tvx[k], wy = vi[1] - tvy[k], wz = vi[2] - tvz[k];
+                    const R xx = -ex, xy = -ey, xz = -ez;
+                    const R wx = svx[s] - tvx[k], wy = svy[s] - tvy[k], wz = svz[s] - tvz[k];
                     const R vdotx = wx * xx + wy * xy + wz * xz;
-                    const R hbar = R(0.25) * (Hi + Hj);
+                    const R hbar = R(0.25) * (Hs_ + Hj);
                     const R mu = hbar * vdotx / (r2 + eps * hbar * hbar);
                     R Pi = 0;
                     if (vdotx < R(0)) {
-                        const R cbar = R(0.5) * (ci + tc[k]);
-                        const R rbar = R(0.5) * (rhoi + trho[k]);
+                        const R cbar = R(0.5) * (sc[s] + tc[k]);
+                        const R rbar = R(0.5) * (srho[s] + trho[k]);
                         Pi = (-alpha * cbar * mu + beta * mu * mu) / rbar;
                     }
                     const R Gbar = R(0.5) * (Gi + Gj);
                     const R mj = tm[k];
-                    const R s = mj * (Ai * Gi + tA[k] * Gj + Pi * Gbar);
-                    p[0] -= s * xx;
-                    p[1] -= s * xy;
-                    p[2] -= s * xz;
-                    p[3] += mj * Gi * vdotx;
-                    p[4] += mj * Pi * Gbar * vdotx;
-                    mumax = -mu > mumax ? -mu : mumax;
-                }
-            }
-            for (int q = 0; q < 5; ++q) {
-                if constexpr (MIXED) neumaier(acc_s[q], acc_c[q], p[q]);
-                else acc_d[q] += p[q];
-            }
+                    const R sc_ = mj * (sA[s] * Gi + tA[k] * Gj + Pi * Gbar);
+                    atomicAdd(&acc[0][s], -sc_ * xx);
+                    atomicAdd(&acc[1][s], -sc_ * xy);
+                    atomicAdd(&acc[2][s], -sc_ * xz);
+                    atomicAdd(&acc[3][s], mj * Gi * vdotx);
+                    atomicAdd(&acc[4][s], mj * Pi * Gbar * vdotx);
+                    if (mu < R(0)) atomicMax(&amu[s], -mu);
+                });
+            };
+            if (MIXED && wrapf) tile(std::true_type{});
+            else tile(std::false_type{});
             __syncthreads();
+            for (int q = 0; q < 5; ++q) {
+                const R v = acc[q][lane];
+                acc[q][lane] = 0;
+                if constexpr (MIXED) neumaier(acc_s[q], acc_c[q], v);
+                else acc_d[q] += v;
+            }
         }
         if (ws.nstack == 0) break;
         ws.ncand = 0;
     }
+    __syncthreads();
+    const R mumax = amu[lane];
     if constexpr (MIXED) {
         for (int q = 0; q < 5; ++q) acc_d[q] = (double)acc_s[q] + (double)acc_c[q];
     }
@@ -675,12 +795,12 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
         if (den > 0.0) dtv = fmin(dtv, a.eta_c * 0.5 * Hd / den);
         a.dt[i] = dtv;
     }
-    // the particle itself passed the distance test once (r = 0, no force)
-    int pairs = wave_sum_i(act ? cnt - 1 : 0);
+    // the particle itself passed the distance test once (r = 0)
+    int pairs_n = wave_sum_i(act ? cnt - 1 : 0);
     int nact = wave_sum_i(act ? 1 : 0);
     if (lane == 0) {
-        atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs);
-        atomicAdd(&a.cnt[C_PAIRS_F_TOT], (unsigned long long)pairs);
+        atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs_n);
+        atomicAdd(&a.cnt[C_PAIRS_F_TOT], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_CAND_F], cand_tested * (unsigned long long)nact);
         if (ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
     }
