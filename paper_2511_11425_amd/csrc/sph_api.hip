@@ -89,7 +89,7 @@ bool valid_params(const sph_params *p, std::string &why) {
 // Topology of buckets, groups and tree nodes for the current n and bucket size.
 sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     Ctx &c = x->c;
-    if (c.n == n && c.allocs.size() > 0) return SPH_OK;
+    if (c.n == n && c.allocs.size() > 0 && c.topo_bucket == c.bucket) return SPH_OK;
     free_all(c);
     const int B = c.bucket;
     const int ns = c.nsets;
@@ -173,7 +173,8 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
     A(c.d_rep, 1);
-    A(c.d_dt, 1);
+    A(c.d_dt, ns);
+    A(c.d_set_dtnext, ns);
     A(c.d_part, 6 * reduce_partials());
 #undef A
     if (e != hipSuccess) { free_all(c); return fail(x, SPH_ERR_OOM, "device allocation failed"); }
@@ -198,6 +199,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     // host pages of the metadata vectors must outlive the copies
     HIPCHK(x, hipStreamSynchronize(s), "setup sync");
     c.n = n;
+    c.topo_bucket = c.bucket;
     return SPH_OK;
 }
 
@@ -284,6 +286,7 @@ sph_status do_step(sph_ctx *x, sph_particles *p, double dt, hipStream_t s) {
     if (st != SPH_OK) return st;
     HIPCHK(x, launch_closing_kick(&c, p, s), "closing kick");
     HIPCHK(x, launch_reduce(&c, p, s), "reduce");
+    HIPCHK(x, launch_set_dtnext(&c, p, s), "set dt");
     mark(&c, E_END, s);
     return SPH_OK;
 }
@@ -447,6 +450,7 @@ sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream) {
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, true, s);
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
+    HIPCHK(ctx, launch_set_dtnext(&c, p, s), "set dt");
     mark(&c, E_END, s);
     c.have_forces = true;
     return SPH_OK;
@@ -466,6 +470,7 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, false, s);
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
+    HIPCHK(ctx, launch_set_dtnext(&c, p, s), "set dt");
     mark(&c, E_END, s);
     c.have_forces = true;
     return SPH_OK;
@@ -568,8 +573,50 @@ sph_status sph_set_timing(sph_ctx *ctx, int32_t enable) {
 }
 
 sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *stream) {
-    (void)ctx; (void)p; (void)bucket; (void)stream;
-    return SPH_ERR_STATE;
+    if (!ctx || !bucket) return SPH_ERR_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Ctx &c = ctx->c;
+    const int64_t n = c.nsets > 1 ? c.set_off.back() : c.n;
+    if (c.nsets == 1 && !c.have_tree)
+        return fail(ctx, SPH_ERR_STATE, "sph_autotune needs a previous sph_build_tree or sph_init");
+    sph_status st = check_particles(ctx, p, true, n);
+    if (st != SPH_OK) return st;
+    if (n == 0) { *bucket = c.bucket; return SPH_OK; }
+    // every trial starts from the same first guess of H
+    double *H0 = nullptr;
+    HIPCHK(ctx, hipMalloc(&H0, sizeof(double) * n), "autotune scratch");
+    hipError_t e = hipMemcpyAsync(H0, p->H, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+    const bool timing = c.timing;
+    st = sph_set_timing(ctx, 1);
+    const int cands[3] = {16, 32, 64};
+    int best = c.bucket;
+    double tbest = 1e300;
+    for (int q = 0; q < 3 && st == SPH_OK && e == hipSuccess; ++q) {
+        c.bucket = cands[q];
+        double t = 1e300;
+        for (int rep = 0; rep < 2 && st == SPH_OK && e == hipSuccess; ++rep) {
+            e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) break;
+            st = sph_init(ctx, p, n, stream);
+            sph_stats ss;
+            if (st == SPH_OK) st = sph_get_stats(ctx, &ss);
+            if (st == SPH_OK && ss.t_density_ms >= 0 && ss.t_forces_ms >= 0)
+                t = std::min(t, ss.t_density_ms + ss.t_forces_ms);
+        }
+        if (t < tbest) { tbest = t; best = cands[q]; }
+    }
+    if (st == SPH_OK && e == hipSuccess) {
+        c.bucket = best;
+        e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) st = sph_init(ctx, p, n, stream);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(H0);
+    c.timing = timing;
+    if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
+    if (st != SPH_OK) return st;
+    *bucket = best;
+    return SPH_OK;
 }
 
 }  // extern "C"

@@ -72,6 +72,7 @@ struct Ctx {
     std::vector<int64_t> set_off;   // host, nsets+1
     std::vector<double> set_box;    // host, 6*nsets (empty = params box)
     int32_t bucket = 32;
+    int32_t topo_bucket = 0;        // bucket size the current allocation was laid out for
     int64_t n = 0;                  // particles of the current allocation
     int64_t nbuckets = 0, ngroups = 0, nnodes = 0;
     int32_t max_depth = 0;
@@ -116,7 +117,8 @@ struct Ctx {
     // counters, step report, reduction partials
     unsigned long long *d_cnt = nullptr;
     StepReport *d_rep = nullptr;
-    double *d_dt = nullptr;         // step size used by the kick kernels
+    double *d_dt = nullptr;         // per set: step size used by the kick kernels
+    double *d_set_dtnext = nullptr; // per set: min_i dt_i of the last force pass
     double *d_part = nullptr;       // reduction partials
     unsigned long long *h_cnt = nullptr; // pinned host mirrors
     StepReport *h_rep = nullptr;
@@ -167,6 +169,7 @@ hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s);
 hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s);
 hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s);
 hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s);
+hipError_t launch_set_dtnext(Ctx *c, const sph_particles *p, hipStream_t s);
 int reduce_partials();
 
 // Records timing event e on stream s when timing is on (no-op otherwise).

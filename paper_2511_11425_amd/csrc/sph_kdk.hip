@@ -17,6 +17,15 @@ constexpr int kRedBlocks = 512;
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+__device__ inline int find_set_k(const SetGeom *sets, int nsets, int64_t i) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sets[mid].p0 <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -67,11 +76,40 @@ __global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, dou
     cc[i] = c;
 }
 
-__global__ void k_set_dt(double dt_in, double dt_max, const StepReport *rep, double *d_dt,
-                         StepReport *rep_out) {
-    double dt = dt_in > 0.0 ? dt_in : fmin(rep->dt_next, dt_max);
-    *d_dt = dt;
-    rep_out->dt_used = dt;
+// Step size of every set: the given dt, else the set's smallest per-particle
+// limit from its last force pass (independent sets keep independent steps).
+__global__ void k_set_dt(double dt_in, double dt_max, const double *set_dtnext, int nsets,
+                         double *d_dt, StepReport *rep) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsets) return;
+    double dt = dt_in > 0.0 ? dt_in : fmin(set_dtnext[s], dt_max);
+    d_dt[s] = dt;
+    if (s == 0) rep->dt_used = dt;
+}
+
+__device__ inline long long dbits(double v) { return __double_as_longlong(v); }
+
+__global__ void k_fill_f64(double *p, int n, double v) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = v;
+}
+
+// Per-set minimum of dt (dt >= 0, so the bit patterns order like the values).
+__global__ void k_set_min_dt(const double *__restrict__ dt, int64_t n, const SetGeom *sets,
+                             int nsets, double *set_min) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = i < n;
+    int s = ok ? (nsets == 1 ? 0 : find_set_k(sets, nsets, i)) : 0;
+    double v = ok ? dt[i] : DBL_MAX;
+    int s0 = __shfl(s, 0);
+    bool uniform = __all(!ok || s == s0);
+    long long *dst = reinterpret_cast<long long *>(set_min);
+    if (uniform) {
+        for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+        if ((threadIdx.x & 63) == 0 && v < DBL_MAX) atomicMin(&dst[s0], dbits(v));
+    } else if (ok) {
+        atomicMin(&dst[s], dbits(v));
+    }
 }
 
 // Opening kick, predictor and drift in caller order (Sec. 2.3.6):
@@ -89,15 +127,6 @@ struct KickArgs {
     int64_t n;
 };
 
-__device__ inline int find_set_k(const SetGeom *sets, int nsets, int64_t i) {
-    int lo = 0, hi = nsets - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (sets[mid].p0 <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ double wrap_box(double v, double lo, double L) {
 #pragma clang fp contract(off)
     double t = floor((v - lo) / L);
@@ -109,7 +138,8 @@ __global__ void k_kick_drift(KickArgs a) {
 #pragma clang fp contract(off)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
-    const double dt = *a.dt;
+    const int sid = a.nsets == 1 ? 0 : find_set_k(a.sets, a.nsets, i);
+    const double dt = a.dt[sid];
     const double hdt = 0.5 * dt;
     double ax = a.ax[i], ay = a.ay[i], az = a.az[i], du = a.du[i];
     double vhx = a.vx[i] + hdt * ax;
@@ -125,7 +155,7 @@ __global__ void k_kick_drift(KickArgs a) {
     double ny = a.y[i] + dt * vhy;
     double nz = a.z[i] + dt * vhz;
     if (a.periodic) {
-        const SetGeom &g = a.sets[a.nsets == 1 ? 0 : find_set_k(a.sets, a.nsets, i)];
+        const SetGeom &g = a.sets[sid];
         nx = wrap_box(nx, g.lo[0], g.L[0]);
         ny = wrap_box(ny, g.lo[1], g.L[1]);
         nz = wrap_box(nz, g.lo[2], g.L[2]);
@@ -134,14 +164,15 @@ __global__ void k_kick_drift(KickArgs a) {
 }
 
 // Closing kick: v = v_half + (dt/2) a_new, u likewise.
-__global__ void k_closing_kick(int64_t n, const double *__restrict__ dtp, double *vx, double *vy,
+__global__ void k_closing_kick(int64_t n, const SetGeom *sets, int nsets,
+                               const double *__restrict__ dtp, double *vx, double *vy,
                                double *vz, double *u, const double *__restrict__ ax,
                                const double *__restrict__ ay, const double *__restrict__ az,
                                const double *__restrict__ du) {
 #pragma clang fp contract(off)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double hdt = 0.5 * (*dtp);
+    const double hdt = 0.5 * dtp[nsets == 1 ? 0 : find_set_k(sets, nsets, i)];
     vx[i] = vx[i] + hdt * ax[i];
     vy[i] = vy[i] + hdt * ay[i];
     vz[i] = vz[i] + hdt * az[i];
@@ -236,7 +267,16 @@ hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *
 }
 
 hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s) {
-    k_set_dt<<<1, 1, 0, s>>>(dt, c->prm.dt_max, c->d_rep, c->d_dt, c->d_rep);
+    k_set_dt<<<nblk(c->nsets, 64), 64, 0, s>>>(dt, c->prm.dt_max, c->d_set_dtnext, c->nsets,
+                                                c->d_dt, c->d_rep);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dtnext(Ctx *c, const sph_particles *p, hipStream_t s) {
+    k_fill_f64<<<nblk(c->nsets, 64), 64, 0, s>>>(c->d_set_dtnext, c->nsets, c->prm.dt_max);
+    if (c->n > 0)
+        k_set_min_dt<<<nblk(c->n, kThreads), kThreads, 0, s>>>(p->dt, c->n, c->d_sets, c->nsets,
+                                                               c->d_set_dtnext);
     return hipGetLastError();
 }
 
@@ -254,8 +294,9 @@ hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s) {
 
 hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s) {
     if (c->n == 0) return hipSuccess;
-    k_closing_kick<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->d_dt, p->vx, p->vy, p->vz,
-                                                             p->u, p->ax, p->ay, p->az, p->dudt);
+    k_closing_kick<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->d_sets, c->nsets, c->d_dt,
+                                                             p->vx, p->vy, p->vz, p->u, p->ax,
+                                                             p->ay, p->az, p->dudt);
     return hipGetLastError();
 }
 
