@@ -97,12 +97,22 @@ def run_gpu(case, precision, steps, warmup):
 
 def cpu_baseline(case, seconds=15.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
-    density (smoothing-length solve) and forces for a random subset of rows."""
+    density (smoothing-length solve) and forces for a random subset of rows,
+    sized from a pilot run to take about `seconds`."""
+    s = case["state"]
+    n = len(s["x"])
+    pilot = _oracle_sample(case, min(n, 20000))
+    per_row = pilot["secs"] / pilot["rows"]
+    rows = int(min(n, max(20000, seconds / max(per_row, 1e-9))))
+    return _oracle_sample(case, rows, final=True)
+
+
+def _oracle_sample(case, nrows, final=False):
     import oracle
     s, p = case["state"], case["params"]
     n = len(s["x"])
     rng = np.random.default_rng(123)
-    rows = np.sort(rng.choice(n, size=2000, replace=False))
+    rows = np.sort(rng.choice(n, size=nrows, replace=False))
     t0 = time.perf_counter()
     d = oracle.solve_h(p, s["x"], s["y"], s["z"], s["m"], s["H"], rows=rows)
     t1 = time.perf_counter()
@@ -118,6 +128,8 @@ def cpu_baseline(case, seconds=15.0):
     t3 = time.perf_counter()
     pairs = int(d["count"].sum() + f["count"].sum())
     secs = (t1 - t0) + (t3 - t2)
+    if not final:
+        return {"rows": rows.size, "secs": secs}
     return {"value": pairs / secs, "unit": "pair interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"{rows.size} random particles of the 128^3 Wendland C4 workload: smoothing-length "
