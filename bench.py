@@ -42,6 +42,47 @@ FLOP_FORCE_PAIR = 84
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}   # MI355X vector peaks (FP32 figure is the packed one)
 
 
+def _ngroups(sizes):
+    return int(sum((int(k) + 63) // 64 for k in sizes))
+
+
+def make_workload(name, small=False):
+    """Synthetic workloads (sph_inputs); `large` is the one the metric is quoted on."""
+    import sph_inputs as si
+    if name == "large":
+        ns = 64 if small else 128
+        c = si.config_large(n_side=ns)
+        c["desc"] = f"{ns}^3 jittered lattice, periodic unit cube, Wendland C4, 200 neighbours"
+    elif name == "two_phase":
+        ns = 64 if small else 128
+        c = si.config_two_phase(n_side=ns)
+        c["desc"] = f"{ns}^3 two-phase slab (density 10 in 1, shear 0.1), Wendland C4, 200 neighbours"
+    elif name == "batch":
+        b = si.config_batch(nsets=32 if small else 256)
+        keys = b["sets"][0].keys()
+        st = {k: np.concatenate([x[k] for x in b["sets"]]) for k in keys}
+        offs = np.concatenate([[0], np.cumsum([len(x["x"]) for x in b["sets"]])]).tolist()
+        c = {"state": st, "params": b["params"], "set_offsets": offs,
+             "desc": f"{len(b['sets'])} independent periodic boxes of 4096-65536 particles, "
+                     f"cubic spline, 64 neighbours"}
+    elif name == "spheres":
+        if small:
+            c = si.config_spheres(n1=1_200_000, n2=480_000)
+        else:
+            c = si.config_spheres()
+        c["desc"] = (f"two spheres of {len(c['state']['x'])} particles in vacuum, stiffened gas, "
+                     f"Wendland C4, 200 neighbours")
+    else:
+        raise ValueError(name)
+    c["n"] = len(c["state"]["x"])
+    offs = c.get("set_offsets") or [0, c["n"]]
+    c["ngroups"] = _ngroups(np.diff(offs))
+    return c
+
+
+WORKLOADS = ("large", "two_phase", "batch", "spheres")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -51,7 +92,7 @@ def run_gpu(case, precision, steps, warmup):
     import paper_2511_11425_amd as sph
     p = dict(case["params"], precision=precision)
     P = sph.ParticleArrays.from_state(case["state"], device="cuda:0")
-    ctx = sph.Context(p)
+    ctx = sph.Context(p, set_offsets=case.get("set_offsets"))
     ctx.init(P)
     for _ in range(warmup):
         ctx.step(P)
@@ -82,7 +123,7 @@ def run_gpu(case, precision, steps, warmup):
         "ms_per_step": 1e3 * wall / steps,
         "pairs_density": st["pairs_density"], "pairs_force": st["pairs_force"],
         "cand_density": st["cand_density"], "cand_force": st["cand_force"],
-        "nr_scans_mean": st["nr_scans"] / max(1, (case["n"] + 63) // 64),
+        "nr_scans_mean": st["nr_scans"] / max(1, case["ngroups"]),
         "nr_iter_max": st["nr_iter_max"], "n_noconv": st["n_noconv"],
         "t_density_ms": float(np.median(tden)), "t_forces_ms": float(np.median(tfor)),
         "t_tree_ms": float(np.median(ttree)), "t_step_ms": float(np.median(ttot)),
@@ -98,7 +139,11 @@ def run_gpu(case, precision, steps, warmup):
 def cpu_baseline(case, seconds=15.0):
     """The FP64 oracle (as it stands) on a bounded sample of the same workload:
     density (smoothing-length solve) and forces for a random subset of rows,
-    sized from a pilot run to take about `seconds`."""
+    sized from a pilot run to take about `seconds` (a batch: its first set)."""
+    if case.get("set_offsets"):
+        o = case["set_offsets"]
+        case = dict(case, state={k: v[o[0]:o[1]] for k, v in case["state"].items()},
+                    desc=case["desc"] + " (first set)")
     s = case["state"]
     n = len(s["x"])
     pilot = _oracle_sample(case, min(n, 20000))
@@ -132,8 +177,9 @@ def _oracle_sample(case, nrows, final=False):
         return {"rows": rows.size, "secs": secs}
     return {"value": pairs / secs, "unit": "pair interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{rows.size} random particles of the 128^3 Wendland C4 workload: smoothing-length "
-                      f"solve + forces, {pairs} pairs in {secs:.1f} s (grid build included)"}
+            "sample": f"{rows.size} random particles of the workload ({case['desc']}): "
+                      f"smoothing-length solve + forces, {pairs} pairs in {secs:.1f} s "
+                      f"(cell-list build included)"}
 
 
 def main():
@@ -144,15 +190,26 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--small", action="store_true", help="64^3 instead of 128^3 (quick check)")
     ap.add_argument("--precisions", default="mixed,fp64")
+    ap.add_argument("--workload", default="large", choices=list(WORKLOADS))
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 5 times (calibrates the HBM "
+                         "FETCH_SIZE/WRITE_SIZE counters against a known byte count)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        nbytes = args.copy_probe << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    import sph_inputs as si
-    n_side = 64 if args.small else 128
-    log(f"generating workload {n_side}^3")
-    case = si.config_large(n_side=n_side)
-    case["n"] = n_side ** 3
+    log(f"generating workload {args.workload}")
+    case = make_workload(args.workload, args.small)
     results = {}
     for prec in args.precisions.split(","):
         log(f"timing {prec}")
@@ -177,15 +234,15 @@ def main():
         cpu = cpu_baseline(case)
     out = {
         "metric": "pair interactions/sec (density+force) at 2M particles; FP32-mixed vs FP64",
+        "workload": args.workload,
         "value": head["pairs_per_s"],
         "unit": "pair interactions/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": f"{n_side}^3 jittered lattice, periodic unit cube, Wendland C4, "
-                               f"200 neighbours, full KDK step, mixed precision",
-                   "particles": n_side ** 3, "parallelism": "single GPU"},
+        "config": {"workload": case["desc"] + ", full KDK step, mixed precision",
+                   "particles": case["n"], "parallelism": "single GPU"},
         "fp64": {k: results["fp64"][k] for k in ("pairs_per_s", "ms_per_step", "metric_rate")}
         if "fp64" in results else None,
         "mixed_vs_fp64": (results["mixed"]["pairs_per_s"] / results["fp64"]["pairs_per_s"])

@@ -88,8 +88,9 @@ typedef struct {
     double h_max;      /* cap on H (also kept below half the periodic box).  Default 0.25. */
     double oversel;    /* the density pass searches with oversel*H so the iteration can
                           grow H without a new walk (Sec. 2.3.3).  Default 1.1. */
-    double nr_tol;     /* relative tolerance on H.  Default 1e-14 (FP64), 1e-6 (mixed)
-                          when left at 0. */
+    double nr_tol;     /* relative tolerance on the Newton step of H.  Default 1e-14
+                          (FP64) or 1e-5 (mixed; the mixed path then applies the final
+                          Newton step to H and rho, leaving O(tol^2) error) when 0. */
     int32_t nr_maxit;  /* iteration cap.  Default 64. */
     int32_t bucket;    /* particles per bucket: 16, 32 or 64; 0 = autotuned.  Default 32. */
 } sph_params;

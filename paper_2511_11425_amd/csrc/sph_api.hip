@@ -153,7 +153,8 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     c.scan_tmp_len = scan_tmp_needed(scan_len);
 
     hipError_t e = hipSuccess;
-#define A(ptr, cnt) if (e == hipSuccess) e = dalloc(c, &(ptr), (cnt))
+    const char *what = "";
+#define A(ptr, cnt) if (e == hipSuccess) { what = #ptr; e = dalloc(c, &(ptr), (cnt)); }
     A(c.d_sets, ns);
     A(c.d_grp_set, grp_set.size());
     A(c.d_bkt_set, bkt_set.size());
@@ -177,7 +178,11 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.d_set_dtnext, ns);
     A(c.d_part, 6 * reduce_partials());
 #undef A
-    if (e != hipSuccess) { free_all(c); return fail(x, SPH_ERR_OOM, "device allocation failed"); }
+    if (e != hipSuccess) {
+        free_all(c);
+        x->c.err = std::string("device allocation failed (") + what + "): " + hipGetErrorString(e);
+        return SPH_ERR_OOM;
+    }
     if (hipHostMalloc((void **)&c.h_cnt, sizeof(unsigned long long) * C_NCOUNTERS) != hipSuccess ||
         hipHostMalloc((void **)&c.h_rep, sizeof(StepReport)) != hipSuccess) {
         free_all(c);
@@ -348,7 +353,7 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
     Ctx &c = x->c;
     c.prm = *params;
     if (!(c.prm.nr_tol > 0))
-        c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-6 : 1e-14;
+        c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-5 : 1e-14;
     c.bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
     c.nsets = nsets;
     if (set_offsets) c.set_off.assign(set_offsets, set_offsets + nsets + 1);

@@ -253,6 +253,53 @@ __device__ __forceinline__ bool group_needs_wrap(bool per, const SetGeom &g, con
     return false;
 }
 
+__device__ __forceinline__ bool point_in_ball(const double *x, const double *c, double R,
+                                              const SetGeom &g, bool per, double slop) {
+    if (!(R >= 0.0)) return false;
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = x[a] - c[a];
+        if (per) d = min_image(d, g.L[a], g.halfL[a]);
+        d2 += d * d;
+    }
+    double Rs = R + slop;
+    return d2 <= Rs * Rs;
+}
+
+// Per-sink refinement of the candidate buckets: the group-level bounds of the
+// walk accept a bucket when it may hold a neighbour of ANY sink; here every
+// lane tests its own ball (gather) and, for the force pass, whether it lies
+// inside the bucket's box-of-balls and ball-of-balls (scatter).  Buckets that
+// no lane needs are dropped (order kept), so the tiles carry fewer candidates.
+template <bool SCATTER>
+__device__ void refine(const SetGeom &g, bool per, double slop, const Node *__restrict__ nodes,
+                       const double *xi, double R, bool act, uint32_t *cand, WalkState &w) {
+    int kept = 0;
+    for (int t = 0; t < w.ncand; ++t) {
+        const uint32_t b = __builtin_amdgcn_readfirstlane(cand[t]);
+        const Node *nd = nodes + g.node0 + g.nbp + ((int64_t)b - g.b0);
+        bool ok = false;
+        if (act) {
+            double clo[3] = {nd->clo[0], nd->clo[1], nd->clo[2]};
+            double chi[3] = {nd->chi[0], nd->chi[1], nd->chi[2]};
+            ok = ball_box(xi, R, clo, chi, g, per, slop);
+            if (SCATTER && !ok) {
+                double blo[3] = {nd->blo[0], nd->blo[1], nd->blo[2]};
+                double bhi[3] = {nd->bhi[0], nd->bhi[1], nd->bhi[2]};
+                double bc[3] = {nd->bc[0], nd->bc[1], nd->bc[2]};
+                ok = ball_box(xi, 0.0, blo, bhi, g, per, slop) &&
+                     point_in_ball(xi, bc, nd->br, g, per, slop);
+            }
+        }
+        if (__any(ok)) {
+            if (threadIdx.x == 0) cand[kept] = b;
+            ++kept;
+        }
+    }
+    w.ncand = kept;
+    __syncthreads();
+}
+
 // Neumaier-compensated accumulation (FP32 partial sums of the mixed path).
 __device__ __forceinline__ void neumaier(float &sum, float &comp, float v) {
     float t = sum + v;
@@ -304,6 +351,9 @@ __device__ __forceinline__ int64_t slot_index(const SetGeom &g, const uint32_t *
     int64_t j = start + off;
     return j < g.p1 ? j : -1;
 }
+
+// Four values staged together so one LDS instruction moves them.
+template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 
 // ================================================================ pair compaction
 //
@@ -382,8 +432,8 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t pairs[kWave * kWave];
-    __shared__ R tx[kWave], ty[kWave], tz[kWave], tm[kWave];
-    __shared__ R sx[kWave], sy[kWave], sz[kWave], sHinv[kWave];
+    __shared__ V4<R> tp[kWave];   // candidate: position, mass
+    __shared__ V4<R> sp[kWave];   // sink: position, 1/H
     __shared__ R accf[kWave], accd[kWave];
 
     const int lane = threadIdx.x;
@@ -430,7 +480,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     } else {
         qx = xi[0]; qy = xi[1]; qz = xi[2];
     }
-    sx[lane] = qx; sy[lane] = qy; sz[lane] = qz;
+    sp[lane] = V4<R>{qx, qy, qz, R(0)};
     accf[lane] = 0; accd[lane] = 0;
     bool wrapf = false;
 
@@ -446,6 +496,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
             sink_bounds(act, xi, Hw, sk);
             walk_reset(stack, ws);
             walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+            refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, ws);
             list_complete = (ws.nstack == 0);
             need_walk = false;
             if constexpr (MIXED) wrapf = group_needs_wrap(per, g, gext, wave_max(act ? Hw : 0.0));
@@ -459,7 +510,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
         const R Hr = (R)H;
         const R Hinv = R(1) / Hr;
         const R H2 = MIXED ? Hr * Hr : (R)(H * H);
-        sHinv[lane] = Hinv;
+        sp[lane].w = Hinv;
         bool first_chunk = true;
         while (true) {
             if (!first_chunk || !list_complete) {
@@ -470,10 +521,12 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                     walk_reset(stack, ws);
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
                 }
+                refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, ws);
             }
             for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
                 int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
                 if (j >= 0) {
+                    const R mj = (R)a.ms[j];
                     if constexpr (MIXED) {
                         double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
                         if (per) {
@@ -481,13 +534,12 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                             d1 = min_image(d1, g.L[1], g.halfL[1]);
                             d2 = min_image(d2, g.L[2], g.halfL[2]);
                         }
-                        tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
+                        tp[lane] = V4<R>{(R)d0, (R)d1, (R)d2, mj};
                     } else {
-                        tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
+                        tp[lane] = V4<R>{a.xs[j], a.ys[j], a.zs[j], mj};
                     }
-                    tm[lane] = (R)a.ms[j];
                 } else {
-                    tx[lane] = (R)NAN; ty[lane] = 0; tz[lane] = 0; tm[lane] = 0;
+                    tp[lane] = V4<R>{(R)NAN, R(0), R(0), R(0)};
                 }
                 cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
                 __syncthreads();
@@ -495,18 +547,21 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                     constexpr bool WRAP = decltype(wrap_tag)::value;
                     R dx, dy, dz;
                     const int T = compact_tile(pairs, [&](int k) {
-                        return pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], qx, qy, qz, per, g,
+                        const V4<R> c = tp[k];
+                        return pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, qx, qy, qz, per, g,
                                                        Lf, hLf, dx, dy, dz) < H2;
                     }, cnt);
                     __syncthreads();
                     for_pairs(pairs, T, [&](int s, int k) {
                         R ex, ey, ez;
-                        const R r2 = pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], sx[s], sy[s],
-                                                             sz[s], per, g, Lf, hLf, ex, ey, ez);
-                        R q = sqrt(r2) * sHinv[s];
+                        const V4<R> c = tp[k];
+                        const V4<R> si = sp[s];
+                        const R r2 = pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, si.x, si.y, si.z, per,
+                                                             g, Lf, hLf, ex, ey, ez);
+                        R q = sqrt(r2) * si.w;
                         R f, qfp;
                         shape_f_qfp<K, R>(q, f, qfp);
-                        const R mj = tm[k];
+                        const R mj = c.w;
                         atomicAdd(&accf[s], mj * f);
                         atomicAdd(&accd[s], mj * (R(3) * f + qfp));
                     });
@@ -607,10 +662,8 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t pairs[kWave * kWave];
-    __shared__ R tx[kWave], ty[kWave], tz[kWave], tvx[kWave], tvy[kWave], tvz[kWave];
-    __shared__ R tm[kWave], tH[kWave], tHi[kWave], tA[kWave], tc[kWave], trho[kWave];
-    __shared__ R sx[kWave], sy[kWave], sz[kWave], svx[kWave], svy[kWave], svz[kWave];
-    __shared__ R sH[kWave], sHi[kWave], sA[kWave], sc[kWave], srho[kWave];
+    __shared__ V4<R> tp[kWave], tv[kWave], tq[kWave];  // candidate: (x m) (v H) (1/H A c rho)
+    __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
     __shared__ R acc[5][kWave];
     __shared__ R amu[kWave];
 
@@ -649,15 +702,10 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
     const R Ai = (R)(act ? a.As[i] : 0.0);
     const R ci = (R)(act ? a.css[i] : 0.0);
     // sink data for the interaction phase
-    sx[lane] = qx; sy[lane] = qy; sz[lane] = qz;
-    svx[lane] = (R)(act ? a.vxs[i] : 0.0);
-    svy[lane] = (R)(act ? a.vys[i] : 0.0);
-    svz[lane] = (R)(act ? a.vzs[i] : 0.0);
-    sH[lane] = Hi;
-    sHi[lane] = act ? R(1) / Hi : R(0);
-    sA[lane] = Ai;
-    sc[lane] = ci;
-    srho[lane] = (R)(act ? a.rhos[i] : 1.0);
+    sp[lane] = V4<R>{qx, qy, qz, Hi};
+    sv[lane] = V4<R>{(R)(act ? a.vxs[i] : 0.0), (R)(act ? a.vys[i] : 0.0),
+                     (R)(act ? a.vzs[i] : 0.0), act ? R(1) / Hi : R(0)};
+    sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), R(0)};
     for (int q = 0; q < 5; ++q) acc[q][lane] = 0;
     amu[lane] = 0;
     const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
@@ -674,9 +722,11 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
 
     while (true) {
         walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, ws);
         for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
             int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
             if (j >= 0) {
+                const R mj = (R)a.ms[j];
                 if constexpr (MIXED) {
                     double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
                     if (per) {
@@ -684,22 +734,17 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                         d1 = min_image(d1, g.L[1], g.halfL[1]);
                         d2 = min_image(d2, g.L[2], g.halfL[2]);
                     }
-                    tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
+                    tp[lane] = V4<R>{(R)d0, (R)d1, (R)d2, mj};
                 } else {
-                    tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
+                    tp[lane] = V4<R>{a.xs[j], a.ys[j], a.zs[j], mj};
                 }
-                double Hj = a.Hs[j];
-                tvx[lane] = (R)a.vxs[j]; tvy[lane] = (R)a.vys[j]; tvz[lane] = (R)a.vzs[j];
-                tm[lane] = (R)a.ms[j];
-                tH[lane] = (R)Hj;
-                tHi[lane] = (R)(1.0 / Hj);
-                tA[lane] = (R)a.As[j];
-                tc[lane] = (R)a.css[j];
-                trho[lane] = (R)a.rhos[j];
+                const double Hj = a.Hs[j];
+                tv[lane] = V4<R>{(R)a.vxs[j], (R)a.vys[j], (R)a.vzs[j], (R)Hj};
+                tq[lane] = V4<R>{(R)(1.0 / Hj), (R)a.As[j], (R)a.css[j], (R)a.rhos[j]};
             } else {
-                tx[lane] = (R)NAN; ty[lane] = 0; tz[lane] = 0;
-                tvx[lane] = 0; tvy[lane] = 0; tvz[lane] = 0;
-                tm[lane] = 0; tH[lane] = 0; tHi[lane] = 0; tA[lane] = 0; tc[lane] = 0; trho[lane] = 1;
+                tp[lane] = V4<R>{(R)NAN, R(0), R(0), R(0)};
+                tv[lane] = V4<R>{R(0), R(0), R(0), R(0)};
+                tq[lane] = V4<R>{R(0), R(0), R(0), R(1)};
             }
             cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
             bool wrapf = false;
@@ -715,9 +760,10 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                 // neighbours but exert no force and no heating (x_ij = 0)
                 int interacting = 0;
                 const int T = compact_tile(pairs, [&](int k) {
-                    const R r2 = pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], qx, qy, qz, per, g,
+                    const V4<R> c = tp[k];
+                    const R r2 = pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, qx, qy, qz, per, g,
                                                          Lf, hLf, dx, dy, dz);
-                    const R Hj = tH[k];
+                    const R Hj = tv[k].w;
                     const R Hj2 = Hj * Hj;
                     const bool in = r2 < (Hi2 > Hj2 ? Hi2 : Hj2);
                     cnt += in ? 1 : 0;
@@ -726,36 +772,38 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                 __syncthreads();
                 for_pairs(pairs, T, [&](int s, int k) {
                     R ex, ey, ez;
-                    const R r2 = pair_r2<MIXED, WRAP, R>(tx[k], ty[k], tz[k], sx[s], sy[s], sz[s],
+                    const V4<R> cp = tp[k], cv = tv[k], cq = tq[k];
+                    const V4<R> ip = sp[s], iv = sv[s], iq = sq[s];
+                    const R r2 = pair_r2<MIXED, WRAP, R>(cp.x, cp.y, cp.z, ip.x, ip.y, ip.z,
                                                          per, g, Lf, hLf, ex, ey, ez);
                     const R r = sqrt(r2);
-                    const R Hs_ = sH[s], Hj = tH[k];
+                    const R Hs_ = ip.w, Hj = cv.w;
                     R Gi = 0, Gj = 0;
                     if (r2 < Hs_ * Hs_) {
-                        const R hinv = sHi[s];
+                        const R hinv = iv.w;
                         const R h2 = hinv * hinv;
                         Gi = sig * shape_g<K, R>(r * hinv, Hs_, r) * (h2 * h2 * hinv);
                     }
                     if (r2 < Hj * Hj) {
-                        const R hinv = tHi[k];
+                        const R hinv = cq.x;
                         const R h2 = hinv * hinv;
                         Gj = sig * shape_g<K, R>(r * hinv, Hj, r) * (h2 * h2 * hinv);
                     }
                     // x_ij = x_i - x_j = -d ; v_ij = v_i - v_j
                     const R xx = -ex, xy = -ey, xz = -ez;
-                    const R wx = svx[s] - tvx[k], wy = svy[s] - tvy[k], wz = svz[s] - tvz[k];
+                    const R wx = iv.x - cv.x, wy = iv.y - cv.y, wz = iv.z - cv.z;
                     const R vdotx = wx * xx + wy * xy + wz * xz;
                     const R hbar = R(0.25) * (Hs_ + Hj);
                     const R mu = hbar * vdotx / (r2 + eps * hbar * hbar);
                     R Pi = 0;
                     if (vdotx < R(0)) {
-                        const R cbar = R(0.5) * (sc[s] + tc[k]);
-                        const R rbar = R(0.5) * (srho[s] + trho[k]);
+                        const R cbar = R(0.5) * (iq.y + cq.z);
+                        const R rbar = R(0.5) * (iq.z + cq.w);
                         Pi = (-alpha * cbar * mu + beta * mu * mu) / rbar;
                     }
                     const R Gbar = R(0.5) * (Gi + Gj);
-                    const R mj = tm[k];
-                    const R sc_ = mj * (sA[s] * Gi + tA[k] * Gj + Pi * Gbar);
+                    const R mj = cp.w;
+                    const R sc_ = mj * (iq.x * Gi + cq.y * Gj + Pi * Gbar);
                     atomicAdd(&acc[0][s], -sc_ * xx);
                     atomicAdd(&acc[1][s], -sc_ * xy);
                     atomicAdd(&acc[2][s], -sc_ * xz);
