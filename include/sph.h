@@ -93,6 +93,10 @@ typedef struct {
                           Newton step to H and rho, leaving O(tol^2) error) when 0. */
     int32_t nr_maxit;  /* iteration cap.  Default 64. */
     int32_t bucket;    /* particles per bucket: 16, 32 or 64; 0 = autotuned.  Default 32. */
+    int32_t stack_limit; /* entries of the per-wavefront walk stack in use, 2..1024 (0 = 1024).
+                            A walk that would outgrow it restarts as a test of every bucket
+                            of the set; results do not change, only the cost. */
+    int32_t reserved;  /* must be 0 */
 } sph_params;
 
 /* Caller-owned device arrays, n doubles each, caller particle order.
@@ -115,7 +119,8 @@ typedef struct {
     int64_t nr_scans;             /* density scans summed over sink groups */
     int64_t n_noconv;             /* particles whose H hit the cap or the iteration limit */
     int64_t n_rewalk;             /* sink groups re-walked because H outgrew the search radius */
-    int64_t n_overflow;           /* walk stack overflows (results invalid if nonzero) */
+    int64_t n_overflow;           /* sink groups whose tree walk outgrew the LDS stack and
+                                     fell back to testing every bucket (results stay exact) */
     double momentum[3];           /* sum m v after the last step (FP64) */
     double e_kin, e_int;          /* sum m v^2/2, sum m u after the last step (FP64) */
     double dt_next;               /* min_i dt_i from the last force pass, capped by dt_max */

@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
         ("alpha", c_double), ("beta", c_double), ("eps_av", c_double),
         ("eta_c", c_double), ("eta_a", c_double), ("dt_max", c_double),
         ("h_max", c_double), ("oversel", c_double), ("nr_tol", c_double),
-        ("nr_maxit", c_int32), ("bucket", c_int32),
+        ("nr_maxit", c_int32), ("bucket", c_int32), ("stack_limit", c_int32),
+        ("reserved", c_int32),
     ]
 
 
@@ -126,7 +127,7 @@ def make_params(p: dict) -> Params:
                  "oversel", "nr_tol"):
         if name in p:
             setattr(q, name, float(p[name]))
-    for name in ("nr_maxit", "bucket"):
+    for name in ("nr_maxit", "bucket", "stack_limit"):
         if name in p:
             setattr(q, name, int(p[name]))
     return q

@@ -83,6 +83,10 @@ bool valid_params(const sph_params *p, std::string &why) {
     if (p->bucket != 0 && p->bucket != 16 && p->bucket != 32 && p->bucket != 64) {
         why = "bucket must be 0, 16, 32 or 64"; return false;
     }
+    if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
+        why = "stack_limit must be 0 or 2..1024"; return false;
+    }
+    if (p->reserved != 0) { why = "reserved must be 0"; return false; }
     return true;
 }
 
@@ -355,6 +359,7 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
     if (!(c.prm.nr_tol > 0))
         c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-5 : 1e-14;
     c.bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    if (c.prm.stack_limit == 0) c.prm.stack_limit = kStackCap;
     c.nsets = nsets;
     if (set_offsets) c.set_off.assign(set_offsets, set_offsets + nsets + 1);
     if (set_box) c.set_box.assign(set_box, set_box + 6 * nsets);

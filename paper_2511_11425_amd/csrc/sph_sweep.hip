@@ -177,16 +177,24 @@ __device__ __forceinline__ bool ball_box(const double *c, double R, const double
 }
 
 // Walk state lives in LDS (stack, candidate list) and in wave-uniform registers.
+// In tree mode `lin` is -1; a group whose stack would overflow restarts in
+// linear mode, where `lin` is the next bucket of the set to test (every bucket
+// is tested once with the same bound tests, so the result does not depend on
+// the stack size).  `nstack > 0` means "more candidates to come" in both modes.
 struct WalkState {
     int nstack;
     int ncand;
+    int lin;
+    int cap;       // stack entries in use (<= kStackCap)
     bool overflow;
 };
 
-__device__ __forceinline__ void walk_reset(uint32_t *stack, WalkState &w) {
+__device__ __forceinline__ void walk_reset(uint32_t *stack, WalkState &w, bool linear) {
     if (threadIdx.x == 0) stack[0] = 1u;
     w.nstack = 1;
     w.ncand = 0;
+    w.lin = linear ? 0 : -1;
+    w.overflow = false;
     __syncthreads();
 }
 
@@ -197,9 +205,36 @@ __device__ void walk(const SetGeom &g, bool per, double slop, const Node *__rest
                      const Sink &sk, uint32_t *stack, uint32_t *cand, WalkState &w) {
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
+    if (w.lin >= 0) {
+        while (w.lin < g.nb && w.ncand <= kCandCap - kWave) {
+            const int b = w.lin + lane;
+            bool ok = false;
+            if (b < g.nb) {
+                const Node *nd = nodes + g.node0 + g.nbp + b;
+                double clo[3] = {nd->clo[0], nd->clo[1], nd->clo[2]};
+                double chi[3] = {nd->chi[0], nd->chi[1], nd->chi[2]};
+                ok = box_box(sk.blo, sk.bhi, clo, chi, g, per, slop) &&
+                     ball_box(sk.bc, sk.br, clo, chi, g, per, slop);
+                if (SCATTER && !ok) {
+                    double blo[3] = {nd->blo[0], nd->blo[1], nd->blo[2]};
+                    double bhi[3] = {nd->bhi[0], nd->bhi[1], nd->bhi[2]};
+                    double bc[3] = {nd->bc[0], nd->bc[1], nd->bc[2]};
+                    ok = box_box(blo, bhi, sk.clo, sk.chi, g, per, slop) &&
+                         ball_box(bc, nd->br, sk.clo, sk.chi, g, per, slop);
+                }
+            }
+            const uint64_t m = __ballot(ok);
+            if (ok) cand[w.ncand + __popcll(m & lt)] = (uint32_t)(g.b0 + b);
+            w.ncand += __popcll(m);
+            w.lin += kWave;
+        }
+        w.nstack = w.lin < g.nb ? 1 : 0;
+        __syncthreads();
+        return;
+    }
     while (w.nstack > 0 && w.ncand <= kCandCap - kWave) {
         int k = w.nstack < kWave ? w.nstack : kWave;
-        if (w.nstack + k > kStackCap) k = kStackCap - w.nstack;
+        if (w.nstack + k > w.cap) k = w.cap - w.nstack;
         if (k <= 0) { w.overflow = true; w.nstack = 0; break; }
         const int base = w.nstack - k;
         uint32_t h = lane < k ? stack[base + lane] : 0u;
@@ -322,6 +357,7 @@ struct SweepArgs {
     int periodic;
     double oversel, tol, h_max, n_ngb;
     int maxit;
+    int stack_limit;
     double alpha, beta, eps, eta_a, eta_c, dt_max;
     // neighbour lists
     int64_t *row_count;     // caller order (count pass)
@@ -484,9 +520,11 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     accf[lane] = 0; accd[lane] = 0;
     bool wrapf = false;
 
-    WalkState ws{0, 0, false};
+    WalkState ws{0, 0, -1, a.stack_limit, false};
     Sink sk;
     bool list_complete = false;
+    bool linear = false;
+    int overflows = 0;
     int scans = 0, rewalks = 0;
     unsigned long long cand_tested = 0;
     bool need_walk = true;
@@ -494,8 +532,14 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     while (true) {
         if (need_walk) {
             sink_bounds(act, xi, Hw, sk);
-            walk_reset(stack, ws);
+            walk_reset(stack, ws, linear);
             walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+            if (ws.overflow) {
+                ++overflows;
+                linear = true;
+                walk_reset(stack, ws, true);
+                walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+            }
             refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, ws);
             list_complete = (ws.nstack == 0);
             need_walk = false;
@@ -518,8 +562,18 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                     ws.ncand = 0;
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
                 } else {
-                    walk_reset(stack, ws);
+                    walk_reset(stack, ws, linear);
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+                }
+                if (ws.overflow) {
+                    // restart this scan with the linear bucket test
+                    ++overflows;
+                    linear = true;
+                    sf_d = sd_d = 0.0;
+                    sf_s = sf_c = sd_s = sd_c = 0.f;
+                    cnt = 0;
+                    first_chunk = true;
+                    continue;
                 }
                 refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, ws);
             }
@@ -650,7 +704,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
         atomicAdd(&a.cnt[C_NR_SCANS], (unsigned long long)scans);
         if (bad) atomicAdd(&a.cnt[C_NOCONV], (unsigned long long)bad);
         if (rewalks) atomicAdd(&a.cnt[C_REWALK], (unsigned long long)rewalks);
-        if (ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
+        if (overflows) atomicAdd(&a.cnt[C_OVERFLOW], (unsigned long long)overflows);
     }
 }
 
@@ -712,16 +766,29 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
 
     Sink sk;
     sink_bounds(act, xi, Hd, sk);
-    WalkState ws{0, 0, false};
-    walk_reset(stack, ws);
+    WalkState ws{0, 0, -1, a.stack_limit, false};
+    bool linear = false;
+    int overflows = 0;
 
     double acc_d[5] = {0, 0, 0, 0, 0};
     float acc_s[5] = {0, 0, 0, 0, 0}, acc_c[5] = {0, 0, 0, 0, 0};
     int cnt = 0;
     unsigned long long cand_tested = 0;
+    walk_reset(stack, ws, linear);
 
     while (true) {
         walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        if (ws.overflow) {
+            // restart the whole pass with the linear bucket test
+            ++overflows;
+            linear = true;
+            for (int q = 0; q < 5; ++q) { acc_d[q] = 0; acc_s[q] = 0; acc_c[q] = 0; }
+            cnt = 0;
+            cand_tested = 0;
+            amu[lane] = 0;
+            walk_reset(stack, ws, true);
+            continue;
+        }
         refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, ws);
         for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
             int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
@@ -850,7 +917,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
         atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_PAIRS_F_TOT], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_CAND_F], cand_tested * (unsigned long long)nact);
-        if (ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
+        if (overflows) atomicAdd(&a.cnt[C_OVERFLOW], (unsigned long long)overflows);
     }
 }
 
@@ -879,11 +946,18 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
 
     Sink sk;
     sink_bounds(act, xi, Hd, sk);
-    WalkState ws{0, 0, false};
-    walk_reset(stack, ws);
+    WalkState ws{0, 0, -1, a.stack_limit, false};
+    walk_reset(stack, ws, false);
     int64_t cnt = 0;
+    int overflows = 0;
     while (true) {
         walk<FORCE>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        if (ws.overflow) {
+            ++overflows;
+            cnt = 0;
+            walk_reset(stack, ws, true);
+            continue;
+        }
         for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
             int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
             tx[lane] = j >= 0 ? a.xs[j] : NAN;
@@ -917,7 +991,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
         ws.ncand = 0;
     }
     if (!FILL && act) a.row_count[orig] = cnt;
-    if (lane == 0 && ws.overflow) atomicAdd(&a.cnt[C_OVERFLOW], 1ull);
+    if (lane == 0 && overflows) atomicAdd(&a.cnt[C_OVERFLOW], (unsigned long long)overflows);
 }
 
 // One workgroup per row: bitonic sort in LDS (rows up to kMaxRow entries).
@@ -972,6 +1046,7 @@ inline SweepArgs base_args(Ctx *c) {
     a.h_max = c->prm.h_max;
     a.n_ngb = c->prm.n_ngb;
     a.maxit = c->prm.nr_maxit;
+    a.stack_limit = c->prm.stack_limit;
     a.alpha = c->prm.alpha; a.beta = c->prm.beta; a.eps = c->prm.eps_av;
     a.eta_a = c->prm.eta_a; a.eta_c = c->prm.eta_c; a.dt_max = c->prm.dt_max;
     return a;

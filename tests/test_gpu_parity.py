@@ -224,3 +224,32 @@ def test_determinism(sph):
         outs.append(P.numpy())
     for k in ("x", "H", "rho", "ax", "dudt", "dt"):
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
+
+
+def test_walk_fallback_is_exact(sph, orc):
+    """A tiny walk stack forces every group onto the linear bucket test; sets
+    stay bit-exact and the density stays within the FP64 bar."""
+    c = cloud(CLOUDS[1])
+    s, p = c["state"], c["params"]
+    P = sph.ParticleArrays.from_state(s)
+    ctx = sph.Context(dict(p, stack_limit=2))
+    ctx.build_tree(P)
+    for mode in (0, 1):
+        off, idx = ctx.neighbors(P, mode)
+        assert ctx.stats()["n_overflow"] > 0
+        ro, ri = orc.neighbors(p, s["x"], s["y"], s["z"], s["H"], mode)
+        np.testing.assert_array_equal(off.cpu().numpy(), ro)
+        np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), ri)
+    ctx.density(P)
+    assert ctx.stats()["n_overflow"] > 0
+    got = P.numpy()
+    ref = orc.solve_h(p, s["x"], s["y"], s["z"], s["m"], s["H"])
+    assert rel(got["rho"], ref["rho"]) < 1e-12
+    st, fref, Pp, cs = force_inputs(orc, c)
+    Q = sph.ParticleArrays.from_state(st)
+    ctx.build_tree(Q)
+    ctx.forces(Q)
+    assert ctx.stats()["n_overflow"] > 0
+    g = Q.numpy()
+    arms = np.sqrt(np.mean(fref["ax"] ** 2 + fref["ay"] ** 2 + fref["az"] ** 2))
+    assert rms_err(g["ax"], fref["ax"], arms) < 1e-12
