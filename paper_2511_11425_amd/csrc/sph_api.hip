@@ -429,7 +429,6 @@ sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int
     HIPCHK(ctx, hipMemcpyAsync(c.h_cnt, c.d_cnt, sizeof(unsigned long long) * C_NCOUNTERS,
                                hipMemcpyDeviceToHost, s), "counters");
     HIPCHK(ctx, hipStreamSynchronize(s), "sync");
-    if (c.h_cnt[C_OVERFLOW]) return fail(ctx, SPH_ERR_CAPACITY, "walk stack overflow");
     if (c.h_cnt[C_ROWLONG]) return fail(ctx, SPH_ERR_CAPACITY, "a row exceeds 4096 entries");
     return SPH_OK;
 }

