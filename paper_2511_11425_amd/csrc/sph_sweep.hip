@@ -72,6 +72,42 @@ __device__ __forceinline__ void shape_f_qfp(R q, R &f, R &qfp) {
     }
 }
 
+// f, t1 = q f'(q) and t2 = 2 q f'(q) + q^2 f''(q): with S0 = sum m f,
+// T1 = sum m t1, T2 = sum m t2 over r < H, d S0/dH = -T1/H and
+// d^2 S0/dH^2 = T2/H^2 (the smoothing-length iteration uses both).
+template <int K, typename R>
+__device__ __forceinline__ void shape_f_t1_t2(R q, R &f, R &t1, R &t2) {
+    R s = R(1) - q;
+    s = s > R(0) ? s : R(0);
+    const R q2 = q * q;
+    if constexpr (K == 0) {
+        if (q < R(0.5)) {
+            f = R(1) + q2 * (R(6) * q - R(6));
+            t1 = q2 * (R(18) * q - R(12));
+            t2 = R(36) * q2 * (R(2) * q - R(1));
+        } else {
+            f = R(2) * s * s * s;
+            t1 = R(-6) * q * s * s;
+            t2 = R(12) * q * s * (R(2) * q - R(1));
+        }
+    } else if constexpr (K == 1) {
+        const R s2 = s * s, s3 = s2 * s;
+        f = s3 * s * (R(1) + R(4) * q);
+        t1 = R(-20) * q2 * s3;
+        t2 = R(60) * q2 * s2 * (R(2) * q - R(1));
+    } else if constexpr (K == 2) {
+        const R s2 = s * s, s4 = s2 * s2, s5 = s4 * s;
+        f = s5 * s * (R(1) + q * (R(6) + q * R(35.0 / 3.0)));
+        t1 = R(-56.0 / 3.0) * q2 * s5 * (R(1) + R(5) * q);
+        t2 = R(56) * q2 * s4 * (q * (R(15) * q - R(4)) - R(1));
+    } else {
+        const R s2 = s * s, s4 = s2 * s2, s6 = s4 * s2, s7 = s6 * s;
+        f = s7 * s * (R(1) + q * (R(8) + q * (R(25) + q * R(32))));
+        t1 = R(-22) * q2 * s7 * (R(1) + q * (R(7) + q * R(16)));
+        t2 = R(66) * q2 * s6 * (q * (q * (R(64) * q - R(1)) - R(6)) - R(1));
+    }
+}
+
 // g(q) = f'(q)/q.  The outer cubic-spline piece (q >= 1/2, so r > 0) needs
 // 1/q = H/r; it is formed only in that branch.
 template <int K, typename R>
@@ -108,13 +144,21 @@ __device__ __forceinline__ double r2_exact(double dx, double dy, double dz) {
     return r2;
 }
 
+// Wave-uniform value moved to scalar registers (the reductions below leave
+// the same value in every lane; saying so frees vector registers).
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
+    return uniform(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    return uniform(v);
 }
 __device__ __forceinline__ int wave_sum_i(int v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -133,7 +177,7 @@ __device__ inline void sink_bounds(bool act, const double *x, double Hw, Sink &s
         sk.chi[a] = wave_max(act ? x[a] : -DBL_MAX);
         sk.blo[a] = wave_min(act ? x[a] - Hw : DBL_MAX);
         sk.bhi[a] = wave_max(act ? x[a] + Hw : -DBL_MAX);
-        sk.bc[a] = 0.5 * (sk.clo[a] + sk.chi[a]);
+        sk.bc[a] = uniform(0.5 * (sk.clo[a] + sk.chi[a]));
     }
     double r = 0.0;
     if (act) {
@@ -407,17 +451,29 @@ template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 //            workgroup, so the order of the adds is fixed).
 // Each sink then folds the tile's partial sums into its own accumulators.
 
+// Pass 1 only reads LDS (the distance tests, so the reads of all 64 staged
+// candidates can be in flight together) and keeps a 64-bit hit mask per lane;
+// pass 2 writes the pairs candidate-major without branches: a lane without
+// the pair writes its own dump slot past the list.
+constexpr int kPairCap = kWave * kWave;
+
 template <class Hit>
 __device__ __forceinline__ int compact_tile(uint16_t *pairs, Hit hit, int &hits) {
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
-    int base = 0;
+    uint32_t mlo = 0, mhi = 0;
 #pragma unroll 8
+    for (int k = 0; k < 32; ++k) mlo |= hit(k) ? (1u << k) : 0u;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) mhi |= hit(32 + k) ? (1u << k) : 0u;
+    hits += __popc(mlo) + __popc(mhi);
+    int base = 0;
+#pragma unroll 16
     for (int k = 0; k < kWave; ++k) {
-        const bool h = hit(k);
+        const bool h = ((k < 32 ? (mlo >> k) : (mhi >> (k - 32))) & 1u) != 0u;
         const uint64_t bal = __ballot(h);
-        if (h) pairs[base + __popcll(bal & lt)] = (uint16_t)((lane << 6) | k);
-        hits += h ? 1 : 0;
+        const int pos = h ? base + __popcll(bal & lt) : kPairCap + lane;
+        pairs[pos] = (uint16_t)((lane << 6) | k);
         base += __popcll(bal);
     }
     return base;
@@ -467,10 +523,10 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
-    __shared__ uint16_t pairs[kWave * kWave];
+    __shared__ uint16_t pairs[kPairCap + kWave];
     __shared__ V4<R> tp[kWave];   // candidate: position, mass
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
-    __shared__ R accf[kWave], accd[kWave];
+    __shared__ R acc0[kWave], acc1[kWave], acc2[kWave];
 
     const int lane = threadIdx.x;
     const int64_t grp = blockIdx.x;
@@ -517,7 +573,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
         qx = xi[0]; qy = xi[1]; qz = xi[2];
     }
     sp[lane] = V4<R>{qx, qy, qz, R(0)};
-    accf[lane] = 0; accd[lane] = 0;
+    acc0[lane] = 0; acc1[lane] = 0; acc2[lane] = 0;
     bool wrapf = false;
 
     WalkState ws{0, 0, -1, a.stack_limit, false};
@@ -548,8 +604,8 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
         // ---- one scan over the candidate list at the lanes' current H.  The
         // particle meets itself (r = 0: f = 1, q f' = 0), which is the self
         // term of the density; it is not counted as a neighbour.
-        double sf_d = 0.0, sd_d = 0.0;
-        float sf_s = 0.f, sf_c = 0.f, sd_s = 0.f, sd_c = 0.f;
+        double S0 = 0.0, T1 = 0.0, T2 = 0.0;
+        float c0s = 0.f, c0c = 0.f, c1s = 0.f, c1c = 0.f, c2s = 0.f, c2c = 0.f;
         int cnt = 0;
         const R Hr = (R)H;
         const R Hinv = R(1) / Hr;
@@ -569,8 +625,8 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                     // restart this scan with the linear bucket test
                     ++overflows;
                     linear = true;
-                    sf_d = sd_d = 0.0;
-                    sf_s = sf_c = sd_s = sd_c = 0.f;
+                    S0 = T1 = T2 = 0.0;
+                    c0s = c0c = c1s = c1c = c2s = c2c = 0.f;
                     cnt = 0;
                     first_chunk = true;
                     continue;
@@ -613,56 +669,72 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                         const R r2 = pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, si.x, si.y, si.z, per,
                                                              g, Lf, hLf, ex, ey, ez);
                         R q = sqrt(r2) * si.w;
-                        R f, qfp;
-                        shape_f_qfp<K, R>(q, f, qfp);
+                        R f, t1, t2;
+                        shape_f_t1_t2<K, R>(q, f, t1, t2);
                         const R mj = c.w;
-                        atomicAdd(&accf[s], mj * f);
-                        atomicAdd(&accd[s], mj * (R(3) * f + qfp));
+                        atomicAdd(&acc0[s], mj * f);
+                        atomicAdd(&acc1[s], mj * t1);
+                        atomicAdd(&acc2[s], mj * t2);
                     });
                 };
                 if (MIXED && wrapf) tile(std::true_type{});
                 else tile(std::false_type{});
                 __syncthreads();
-                const R pf = accf[lane], pd = accd[lane];
-                accf[lane] = 0; accd[lane] = 0;
+                const R p0 = acc0[lane], p1 = acc1[lane], p2 = acc2[lane];
+                acc0[lane] = 0; acc1[lane] = 0; acc2[lane] = 0;
                 if constexpr (MIXED) {
-                    neumaier(sf_s, sf_c, pf);
-                    neumaier(sd_s, sd_c, pd);
+                    neumaier(c0s, c0c, p0);
+                    neumaier(c1s, c1c, p1);
+                    neumaier(c2s, c2c, p2);
                 } else {
-                    sf_d += pf;
-                    sd_d += pd;
+                    S0 += p0;
+                    T1 += p1;
+                    T2 += p2;
                 }
             }
             first_chunk = false;
             if (ws.nstack == 0) break;  // walk finished
         }
         if constexpr (MIXED) {
-            sf_d += (double)sf_s + (double)sf_c;
-            sd_d += (double)sd_s + (double)sd_c;
+            S0 = (double)c0s + (double)c0c;
+            T1 = (double)c1s + (double)c1c;
+            T2 = (double)c2s + (double)c2c;
         }
         ++scans;
-        // ---- Newton update per lane (bracketed, Sec. 2.3.3)
+        // ---- Halley update per lane, safeguarded by a bracket (Sec. 2.3.3:
+        // Newton-Raphson on the constant kernel mass; the second derivative
+        // of the same sums makes the update cubically convergent).
+        //   F = (4 pi/3) sigma S0 - n_ngb m,  F' = -(4 pi/3) sigma T1 / H,
+        //   F'' = (4 pi/3) sigma T2 / H^2,  rho = sigma S0 / H^3,
+        //   Omega = 1 + H rho'/(3 rho) = -T1 / (3 S0).
         bool want_walk = false;
         if (!done) {
             const double H3 = H * H * H;
-            const double rh = sig * sf_d / H3;
-            const double drh = -sig * sd_d / (H3 * H);
-            const double omg = 1.0 + H * drh / (3.0 * rh);
-            const double F = c43 * H3 * rh - target;
-            const double dF = 4.0 * kPi * H * H * rh * omg;
-            rho = rh; om = omg; cnt_out = cnt - 1;
+            const double c0 = c43 * sig;
+            const double F = c0 * S0 - target;
+            const double dF = -c0 * T1 / H;
+            const double d2F = c0 * T2 / (H * H);
+            rho = sig * S0 / H3;
+            om = -T1 / (3.0 * S0);
+            cnt_out = cnt - 1;
             if (F < 0.0) lo = H; else { hi = H; hi_ok = true; }
-            // Newton step; the stopping test looks at the step before the
-            // bracket safeguard (a step below the spacing of doubles leaves
-            // H - step == H, which must not read as leaving the bracket)
-            const double step = dF > 0.0 ? F / dF : NAN;
-            if (F == 0.0 || fabs(step) <= a.tol * H) {
+            // Newton step for the stopping test (before the bracket safeguard:
+            // a step below the spacing of doubles leaves H - step == H)
+            const double newton = dF > 0.0 ? F / dF : NAN;
+            const double den = 2.0 * dF * dF - F * d2F;
+            const double step = (dF > 0.0 && den > 0.0) ? 2.0 * F * dF / den : newton;
+            if (F == 0.0 || (!MIXED && fabs(newton) <= a.tol * H)) {
                 done = true;
-                if constexpr (MIXED) {
-                    // take the final Newton correction too (FP32 sums resolve ~1e-7)
-                    rho = rh - drh * step;
-                    H = H - step;
-                }
+            } else if (MIXED && fabs(step) <= 2e-3 * H) {
+                // one Halley step leaves O((step/H)^3) error; the sums at the new
+                // H follow from their derivatives (S0'' = T2/H^2, T1' = -(T2-T1)/H)
+                done = true;
+                const double dH = -step;
+                const double S0n = S0 - T1 / H * dH + 0.5 * T2 / (H * H) * dH * dH;
+                const double T1n = T1 - (T2 - T1) / H * dH;
+                H = H + dH;
+                rho = sig * S0n / (H * H * H);
+                om = -T1n / (3.0 * S0n);
             } else if (F < 0.0 && H >= cap) {
                 done = true;   // the root lies beyond the cap
                 noconv = true;
@@ -715,7 +787,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
-    __shared__ uint16_t pairs[kWave * kWave];
+    __shared__ uint16_t pairs[kPairCap + kWave];
     __shared__ V4<R> tp[kWave], tv[kWave], tq[kWave];  // candidate: (x m) (v H) (1/H A c rho)
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
     __shared__ R acc[5][kWave];
