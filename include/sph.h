@@ -158,7 +158,7 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
 /* Frees the context and all device memory it owns (synchronises the device). */
 void sph_destroy(sph_ctx *ctx);
 
-/* Tree build (Sec. 2.1, Sec. 2.3.2): Morton keys of x y z within the box,
+/* Tree build (Sec. 2.1, Sec. 2.3.2): Hilbert keys of x y z within the box,
  * stable radix sort, gather into sorted order, buckets of `bucket` particles,
  * cell bounds, box-of-balls and ball-of-balls from H, combined bottom-up over
  * a binary tree of buckets.  Reads x y z m H.  n must equal the set total for

@@ -150,7 +150,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     }
     c.set_bits = 0;
     while ((1 << c.set_bits) < ns) ++c.set_bits;
-    int key_bits = 3 * morton_bits() + c.set_bits;
+    int key_bits = 3 * key_bits_per_axis() + c.set_bits;
     c.key_passes = (key_bits + 7) / 8;
     c.sort_blocks = sort_blocks_needed(n);
     int64_t scan_len = std::max<int64_t>(n + 1, 256 * std::max<int64_t>(c.sort_blocks, 1));

@@ -144,7 +144,7 @@ hipError_t launch_init_nodes(Ctx *c, hipStream_t s);
 hipError_t launch_scan_i64(Ctx *c, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 int64_t scan_tmp_needed(int64_t n);
 int64_t sort_blocks_needed(int64_t n);
-int morton_bits();
+int key_bits_per_axis();
 
 // Sweep (sph_sweep.hip)
 hipError_t launch_density(Ctx *c, hipStream_t s);

@@ -1,5 +1,5 @@
 // sph_kdk.hip -- elementwise passes of the step: gathers into and scatters out
-// of Morton order, the equation of state (Sec. 2.3.1), the kick-drift-kick
+// of Hilbert order, the equation of state (Sec. 2.3.1), the kick-drift-kick
 // integrator with the velocity/energy predictor (Sec. 2.3.6), and the FP64
 // reductions of momentum, energy and the global time step.  All of these are
 // HBM-bound streams; they are kept separate from the sweep so the same

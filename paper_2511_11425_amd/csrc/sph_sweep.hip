@@ -1,6 +1,6 @@
 // sph_sweep.hip -- the neighbour-interaction sweep on gfx950.
 //
-//   walk      one wavefront per sink group of 64 consecutive (Morton-ordered)
+//   walk      one wavefront per sink group of 64 consecutive (Hilbert-ordered)
 //             particles walks its set's bucket tree with the bound-overlap
 //             tests of Sec. 2.3.2 / Fig. 1: gather = sink box-of-balls AND
 //             sink ball-of-balls overlap the source cell bound; scatter =

@@ -3,10 +3,15 @@
 // box-of-balls and ball-of-balls combined bottom-up).
 //
 // MI355X design: instead of a top-down recursive bisection, particles are
-// ordered along a Morton curve (16 bits per axis, set id in the high bits) by
+// ordered along a Hilbert curve (16 bits per axis, set id in the high bits) by
 // a hand-written stable LSD radix sort, cut into buckets of B consecutive
 // particles, and an implicit binary tree (heap layout) is laid over the
-// buckets of each set.  Every node is then a contiguous particle range, as in
+// buckets of each set.  Fixed-size runs of a space-filling order are compact
+// only if the curve has no long jumps: on a Morton curve a run that crosses
+// the boundary of a large octant spans far-apart regions, and once particles
+// drift off their lattice cells most runs are unaligned.  Consecutive Hilbert
+// cells always share a face, so every bucket and every sink group stays a
+// connected, compact region.  Every node is then a contiguous particle range, as in
 // the paper, and bounds are combined level by level with one launch per
 // tree height across all sets.
 #include "sph_internal.h"
@@ -20,7 +25,7 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kMortonBits = 16;
+constexpr int kKeyBits = 16;
 
 __device__ inline uint64_t spread3(uint64_t v) {
     v &= 0x1fffffull;
@@ -30,6 +35,33 @@ __device__ inline uint64_t spread3(uint64_t v) {
     v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
     v = (v | (v << 2)) & 0x1249249249249249ull;
     return v;
+}
+
+// Hilbert index of a cell with integer coordinates X[0..2] (kKeyBits each),
+// after J. Skilling, "Programming the Hilbert curve", AIP Conf. Proc. 707
+// (2004): the coordinates are transformed in place into the "transposed"
+// index (bit j of X[0], X[1], X[2] are the index bits 3j+2, 3j+1, 3j), which
+// is then interleaved.
+__device__ inline uint64_t hilbert_key(uint32_t X[3]) {
+    for (uint32_t Q = 1u << (kKeyBits - 1); Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;                       // invert the low bits of X[0]
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;   // swap low bits of X[0], X[i]
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];                                // Gray encode
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = 1u << (kKeyBits - 1); Q > 1u; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1u;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    return (spread3(X[0]) << 2) | (spread3(X[1]) << 1) | spread3(X[2]);
 }
 
 __device__ inline int find_set(const SetGeom *sets, int nsets, int64_t i) {
@@ -105,7 +137,7 @@ __global__ void k_bbox_finish(const long long *enc, SetGeom *sets, int nsets) {
     }
 }
 
-__global__ void k_morton(const double *__restrict__ x, const double *__restrict__ y,
+__global__ void k_sfc_keys(const double *__restrict__ x, const double *__restrict__ y,
                          const double *__restrict__ z, int64_t n, const SetGeom *sets, int nsets,
                          uint64_t *keys, uint32_t *perm) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,15 +145,15 @@ __global__ void k_morton(const double *__restrict__ x, const double *__restrict_
     int s = nsets == 1 ? 0 : find_set(sets, nsets, i);
     const SetGeom &g = sets[s];
     double v[3] = {x[i], y[i], z[i]};
-    uint64_t key = 0;
-    const double scale = (double)(1u << kMortonBits);
+    uint32_t X[3];
+    const double scale = (double)(1u << kKeyBits);
     for (int a = 0; a < 3; ++a) {
         double t = floor((v[a] - g.lo[a]) / g.L[a] * scale);
         if (!(t >= 0.0)) t = 0.0;
         if (t > scale - 1.0) t = scale - 1.0;
-        key |= spread3((uint64_t)t) << a;
+        X[a] = (uint32_t)t;
     }
-    keys[i] = ((uint64_t)s << (3 * kMortonBits)) | key;
+    keys[i] = ((uint64_t)s << (3 * kKeyBits)) | hilbert_key(X);
     perm[i] = (uint32_t)i;
 }
 
@@ -383,7 +415,7 @@ hipError_t launch_scan_i64(Ctx *c, const int64_t *in, int64_t *out, int64_t n, h
 
 int64_t scan_tmp_needed(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 int64_t sort_blocks_needed(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
-int morton_bits() { return kMortonBits; }
+int key_bits_per_axis() { return kKeyBits; }
 
 hipError_t launch_init_nodes(Ctx *c, hipStream_t s) {
     k_nodes_empty<<<nblk(c->nnodes, 256), 256, 0, s>>>(c->nodes, c->nnodes);
@@ -414,7 +446,7 @@ hipError_t launch_tree_build(Ctx *c, const sph_particles *p, hipStream_t s) {
         k_bbox<<<nblk(n, 256), 256, 0, s>>>(p->x, p->y, p->z, n, c->d_sets, c->nsets, enc);
         k_bbox_finish<<<nblk(c->nsets, 64), 64, 0, s>>>(enc, c->d_sets, c->nsets);
     }
-    k_morton<<<nblk(n, 256), 256, 0, s>>>(p->x, p->y, p->z, n, c->d_sets, c->nsets, c->d_key[0],
+    k_sfc_keys<<<nblk(n, 256), 256, 0, s>>>(p->x, p->y, p->z, n, c->d_sets, c->nsets, c->d_key[0],
                                           c->d_perm[0]);
     int cur = 0;
     const int64_t nb = c->sort_blocks;
