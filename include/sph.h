@@ -92,7 +92,7 @@ typedef struct {
                           (FP64) or 1e-5 (mixed; the mixed path then applies the final
                           Newton step to H and rho, leaving O(tol^2) error) when 0. */
     int32_t nr_maxit;  /* iteration cap.  Default 64. */
-    int32_t bucket;    /* particles per bucket: 16, 32 or 64; 0 = autotuned.  Default 32. */
+    int32_t bucket;    /* particles per bucket: 8, 16, 32 or 64; 0 = autotuned.  Default 32. */
     int32_t stack_limit; /* entries of the per-wavefront walk stack in use, 2..1024 (0 = 1024).
                             A walk that would outgrow it restarts as a test of every bucket
                             of the set; results do not change, only the cost. */

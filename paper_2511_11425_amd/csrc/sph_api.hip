@@ -80,8 +80,8 @@ bool valid_params(const sph_params *p, std::string &why) {
     if (!(p->oversel >= 1.0)) { why = "oversel must be >= 1"; return false; }
     if (!(p->gamma > 1.0)) { why = "gamma must exceed 1"; return false; }
     if (p->nr_maxit < 1) { why = "nr_maxit must be >= 1"; return false; }
-    if (p->bucket != 0 && p->bucket != 16 && p->bucket != 32 && p->bucket != 64) {
-        why = "bucket must be 0, 16, 32 or 64"; return false;
+    if (p->bucket != 0 && p->bucket != 8 && p->bucket != 16 && p->bucket != 32 && p->bucket != 64) {
+        why = "bucket must be 0, 8, 16, 32 or 64"; return false;
     }
     if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
         why = "stack_limit must be 0 or 2..1024"; return false;
@@ -597,10 +597,10 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     hipError_t e = hipMemcpyAsync(H0, p->H, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     const bool timing = c.timing;
     st = sph_set_timing(ctx, 1);
-    const int cands[3] = {16, 32, 64};
+    const int cands[4] = {8, 16, 32, 64};
     int best = c.bucket;
     double tbest = 1e300;
-    for (int q = 0; q < 3 && st == SPH_OK && e == hipSuccess; ++q) {
+    for (int q = 0; q < 4 && st == SPH_OK && e == hipSuccess; ++q) {
         c.bucket = cands[q];
         double t = 1e300;
         for (int rep = 0; rep < 2 && st == SPH_OK && e == hipSuccess; ++rep) {

@@ -443,9 +443,9 @@ template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 // only ~15% of the (sink, candidate) pairs are neighbours.  The sweep
 // therefore runs two phases per tile:
 //   test     lane = sink, candidates by LDS broadcast, distance test only;
-//            the accepted pairs of each candidate are ballot-compacted into an
-//            LDS pair list, candidate-major (so consecutive entries rarely
-//            share a sink);
+//            the accepted pairs are compacted into an LDS pair list in rounds:
+//            round r holds the r-th accepted candidate of every lane that has
+//            one, so entries of a round have distinct sinks;
 //   interact lane = pair: 64 accepted pairs per step, contributions added to
 //            the sink's LDS accumulator with LDS float atomics (one wave per
 //            workgroup, so the order of the adds is fixed).
@@ -453,47 +453,70 @@ template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 
 // Pass 1 only reads LDS (the distance tests, so the reads of all 64 staged
 // candidates can be in flight together) and keeps a 64-bit hit mask per lane;
-// pass 2 writes the pairs candidate-major without branches: a lane without
-// the pair writes its own dump slot past the list.
+// pass 2 takes one accepted candidate per lane and round (lowest set bit) and
+// stops after as many rounds as the largest per-lane count, typically far
+// fewer than 64.
 constexpr int kPairCap = kWave * kWave;
 
-template <class Hit>
-__device__ __forceinline__ int compact_tile(uint16_t *pairs, Hit hit, int &hits) {
+// `hit8(k0)` returns the accepted bits of candidates k0..k0+7 of this lane.
+template <class Hit8>
+__device__ __forceinline__ int compact_tile(uint16_t *pairs, Hit8 hit8, int &hits) {
     const int lane = threadIdx.x;
-    const uint64_t lt = (1ull << lane) - 1ull;
-    uint32_t mlo = 0, mhi = 0;
-#pragma unroll 8
-    for (int k = 0; k < 32; ++k) mlo |= hit(k) ? (1u << k) : 0u;
-#pragma unroll 8
-    for (int k = 0; k < 32; ++k) mhi |= hit(32 + k) ? (1u << k) : 0u;
-    hits += __popc(mlo) + __popc(mhi);
+    uint64_t m = 0;
+#pragma unroll 2
+    for (int k0 = 0; k0 < kWave; k0 += 8) m |= (uint64_t)hit8(k0) << k0;
+    hits += __popcll(m);
     int base = 0;
-#pragma unroll 16
-    for (int k = 0; k < kWave; ++k) {
-        const bool h = ((k < 32 ? (mlo >> k) : (mhi >> (k - 32))) & 1u) != 0u;
+    for (;;) {
+        const bool h = m != 0ull;
         const uint64_t bal = __ballot(h);
-        const int pos = h ? base + __popcll(bal & lt) : kPairCap + lane;
-        pairs[pos] = (uint16_t)((lane << 6) | k);
+        if (bal == 0ull) break;
+        if (h) {
+            const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            pairs[base + below] = (uint16_t)((lane << 6) | __builtin_ctzll(m));
+            m &= m - 1ull;
+        }
         base += __popcll(bal);
     }
     return base;
 }
 
-template <class Pair>
-__device__ __forceinline__ void for_pairs(const uint16_t *pairs, int T, Pair f) {
-    for (int c = 0; c < T; c += kWave) {
-        const int t = c + (int)threadIdx.x;
-        if (t < T) {
-            const uint16_t p = pairs[t];
-            f((int)(p >> 6), (int)(p & 63));
+// Interaction phase: U chunks of 64 pairs per step, all operands of the U
+// pairs fetched from LDS before any is used (so their latencies overlap).
+// Lanes past the end fetch pair 0 and apply nothing.
+template <int U, class Fetch, class Apply>
+__device__ __forceinline__ void for_pairs(const uint16_t *pairs, int T, Fetch fetch, Apply apply) {
+    const int lane = threadIdx.x;
+    for (int c = 0; c < T; c += U * kWave) {
+        decltype(fetch(0, 0)) d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = c + u * kWave + lane;
+            const uint16_t p = pairs[t < T ? t : 0];
+            d[u] = fetch((int)(p >> 6), (int)(p & 63));
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (u == 0 || c + u * kWave < T) apply(d[u], c + u * kWave + lane < T);
     }
 }
 
+// Four consecutive entries of an LDS array (one 128-bit read for FP32).
+template <typename R>
+__device__ __forceinline__ V4<R> ld4(const R *p) { return *reinterpret_cast<const V4<R> *>(p); }
+
+// Square root of the pair distance: the hardware instruction in FP32 (within
+// one ulp, the mixed path's tolerance is far wider), IEEE in FP64.
+__device__ __forceinline__ float pair_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double pair_sqrt(double x) { return sqrt(x); }
+
 // Pair difference d = x_k - x_i (candidate minus sink).  FP64: absolute
-// coordinates, minimum image, distance without contraction.  Mixed: FP32
-// coordinates relative to the group centre, re-wrapped only when the group is
-// too wide for the single image chosen at staging.
+// coordinates, minimum image, distance without contraction (the sets are
+// bit-exact).  Mixed: FP32 coordinates relative to the group centre,
+// re-wrapped only when the group is too wide for the single image chosen at
+// staging; r^2 with fused multiply-adds (the same expression for the test and
+// the interaction, and symmetric in i and j).
 template <bool MIXED, bool WRAP, typename R>
 __device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool per,
                                      const SetGeom &g, const R *Lf, const R *hLf,
@@ -505,7 +528,7 @@ __device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool pe
             dy = wrap_f(dy, Lf[1], hLf[1]);
             dz = wrap_f(dz, Lf[2], hLf[2]);
         }
-        return dx * dx + dy * dy + dz * dz;
+        return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     } else {
         if (per) {
             dx = min_image(dx, g.L[0], g.halfL[0]);
@@ -524,7 +547,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t pairs[kPairCap + kWave];
-    __shared__ V4<R> tp[kWave];   // candidate: position, mass
+    __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], tm[kWave];  // candidates
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
     __shared__ R acc0[kWave], acc1[kWave], acc2[kWave];
 
@@ -644,37 +667,49 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                             d1 = min_image(d1, g.L[1], g.halfL[1]);
                             d2 = min_image(d2, g.L[2], g.halfL[2]);
                         }
-                        tp[lane] = V4<R>{(R)d0, (R)d1, (R)d2, mj};
+                        tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2; tm[lane] = mj;
                     } else {
-                        tp[lane] = V4<R>{a.xs[j], a.ys[j], a.zs[j], mj};
+                        tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j]; tm[lane] = mj;
                     }
                 } else {
-                    tp[lane] = V4<R>{(R)NAN, R(0), R(0), R(0)};
+                    tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
                 }
                 cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
                 __syncthreads();
                 auto tile = [&](auto wrap_tag) {
                     constexpr bool WRAP = decltype(wrap_tag)::value;
-                    R dx, dy, dz;
-                    const int T = compact_tile(pairs, [&](int k) {
-                        const V4<R> c = tp[k];
-                        return pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, qx, qy, qz, per, g,
-                                                       Lf, hLf, dx, dy, dz) < H2;
+                    auto in = [&](R x, R y, R z) -> uint32_t {
+                        R dx, dy, dz;
+                        return pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
+                                                       dx, dy, dz) < H2 ? 1u : 0u;
+                    };
+                    const int T = compact_tile(pairs, [&](int k0) {
+                        uint32_t b = 0;
+#pragma unroll
+                        for (int h = 0; h < 8; h += 4) {
+                            const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
+                                        Z = ld4(tz + k0 + h);
+                            b |= (in(X.x, Y.x, Z.x) | in(X.y, Y.y, Z.y) << 1 |
+                                  in(X.z, Y.z, Z.z) << 2 | in(X.w, Y.w, Z.w) << 3) << h;
+                        }
+                        return b;
                     }, cnt);
                     __syncthreads();
-                    for_pairs(pairs, T, [&](int s, int k) {
+                    struct PD { int s; R x, y, z, m; V4<R> si; };
+                    for_pairs<MIXED ? 2 : 1>(pairs, T, [&](int s, int k) {
+                        return PD{s, tx[k], ty[k], tz[k], tm[k], sp[s]};
+                    }, [&](const PD &d, bool valid) {
                         R ex, ey, ez;
-                        const V4<R> c = tp[k];
-                        const V4<R> si = sp[s];
-                        const R r2 = pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, si.x, si.y, si.z, per,
-                                                             g, Lf, hLf, ex, ey, ez);
-                        R q = sqrt(r2) * si.w;
+                        const R r2 = pair_r2<MIXED, WRAP, R>(d.x, d.y, d.z, d.si.x, d.si.y,
+                                                             d.si.z, per, g, Lf, hLf, ex, ey, ez);
+                        const R q = pair_sqrt(r2) * d.si.w;
                         R f, t1, t2;
                         shape_f_t1_t2<K, R>(q, f, t1, t2);
-                        const R mj = c.w;
-                        atomicAdd(&acc0[s], mj * f);
-                        atomicAdd(&acc1[s], mj * t1);
-                        atomicAdd(&acc2[s], mj * t2);
+                        if (valid) {
+                            atomicAdd(&acc0[d.s], d.m * f);
+                            atomicAdd(&acc1[d.s], d.m * t1);
+                            atomicAdd(&acc2[d.s], d.m * t2);
+                        }
                     });
                 };
                 if (MIXED && wrapf) tile(std::true_type{});
@@ -788,7 +823,9 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t pairs[kPairCap + kWave];
-    __shared__ V4<R> tp[kWave], tv[kWave], tq[kWave];  // candidate: (x m) (v H) (1/H A c rho)
+    // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho)
+    __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], th2[kWave], tm[kWave];
+    __shared__ V4<R> tv[kWave], tq[kWave];
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
     __shared__ R acc[5][kWave];
     __shared__ R amu[kWave];
@@ -873,15 +910,19 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                         d1 = min_image(d1, g.L[1], g.halfL[1]);
                         d2 = min_image(d2, g.L[2], g.halfL[2]);
                     }
-                    tp[lane] = V4<R>{(R)d0, (R)d1, (R)d2, mj};
+                    tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
                 } else {
-                    tp[lane] = V4<R>{a.xs[j], a.ys[j], a.zs[j], mj};
+                    tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
                 }
+                tm[lane] = mj;
                 const double Hj = a.Hs[j];
-                tv[lane] = V4<R>{(R)a.vxs[j], (R)a.vys[j], (R)a.vzs[j], (R)Hj};
+                const R Hjr = (R)Hj;
+                th2[lane] = MIXED ? Hjr * Hjr : (R)(Hj * Hj);
+                tv[lane] = V4<R>{(R)a.vxs[j], (R)a.vys[j], (R)a.vzs[j], Hjr};
                 tq[lane] = V4<R>{(R)(1.0 / Hj), (R)a.As[j], (R)a.css[j], (R)a.rhos[j]};
             } else {
-                tp[lane] = V4<R>{(R)NAN, R(0), R(0), R(0)};
+                tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
+                th2[lane] = R(0);
                 tv[lane] = V4<R>{R(0), R(0), R(0), R(0)};
                 tq[lane] = V4<R>{R(0), R(0), R(0), R(1)};
             }
@@ -894,28 +935,41 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
             __syncthreads();
             auto tile = [&](auto wrap_tag) {
                 constexpr bool WRAP = decltype(wrap_tag)::value;
-                R dx, dy, dz;
                 // r = 0 pairs (the particle itself, or a coincident one) count as
                 // neighbours but exert no force and no heating (x_ij = 0)
+                auto in = [&](R x, R y, R z, R h2, uint32_t &nb) -> uint32_t {
+                    R dx, dy, dz;
+                    const R r2 = pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
+                                                         dx, dy, dz);
+                    const bool inside = r2 < Hi2 || r2 < h2;
+                    nb += inside ? 1u : 0u;
+                    return (inside && r2 > R(0)) ? 1u : 0u;
+                };
                 int interacting = 0;
-                const int T = compact_tile(pairs, [&](int k) {
-                    const V4<R> c = tp[k];
-                    const R r2 = pair_r2<MIXED, WRAP, R>(c.x, c.y, c.z, qx, qy, qz, per, g,
-                                                         Lf, hLf, dx, dy, dz);
-                    const R Hj = tv[k].w;
-                    const R Hj2 = Hj * Hj;
-                    const bool in = r2 < (Hi2 > Hj2 ? Hi2 : Hj2);
-                    cnt += in ? 1 : 0;
-                    return in && r2 > R(0);
+                const int T = compact_tile(pairs, [&](int k0) {
+                    uint32_t b = 0, nb = 0;
+#pragma unroll
+                    for (int h = 0; h < 8; h += 4) {
+                        const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
+                                    Z = ld4(tz + k0 + h), W = ld4(th2 + k0 + h);
+                        b |= (in(X.x, Y.x, Z.x, W.x, nb) | in(X.y, Y.y, Z.y, W.y, nb) << 1 |
+                              in(X.z, Y.z, Z.z, W.z, nb) << 2 | in(X.w, Y.w, Z.w, W.w, nb) << 3)
+                             << h;
+                    }
+                    cnt += (int)nb;
+                    return b;
                 }, interacting);
                 __syncthreads();
-                for_pairs(pairs, T, [&](int s, int k) {
+                struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
+                for_pairs<MIXED ? 2 : 1>(pairs, T, [&](int s, int k) {
+                    return PF{s, tx[k], ty[k], tz[k], tm[k], tv[k], tq[k], sp[s], sv[s], sq[s]};
+                }, [&](const PF &d, bool valid) {
+                    const int s = d.s;
+                    const V4<R> &cv = d.cv, &cq = d.cq, &ip = d.ip, &iv = d.iv, &iq = d.iq;
                     R ex, ey, ez;
-                    const V4<R> cp = tp[k], cv = tv[k], cq = tq[k];
-                    const V4<R> ip = sp[s], iv = sv[s], iq = sq[s];
-                    const R r2 = pair_r2<MIXED, WRAP, R>(cp.x, cp.y, cp.z, ip.x, ip.y, ip.z,
+                    const R r2 = pair_r2<MIXED, WRAP, R>(d.x, d.y, d.z, ip.x, ip.y, ip.z,
                                                          per, g, Lf, hLf, ex, ey, ez);
-                    const R r = sqrt(r2);
+                    const R r = pair_sqrt(r2);
                     const R Hs_ = ip.w, Hj = cv.w;
                     R Gi = 0, Gj = 0;
                     if (r2 < Hs_ * Hs_) {
@@ -941,14 +995,16 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                         Pi = (-alpha * cbar * mu + beta * mu * mu) / rbar;
                     }
                     const R Gbar = R(0.5) * (Gi + Gj);
-                    const R mj = cp.w;
+                    const R mj = d.m;
                     const R sc_ = mj * (iq.x * Gi + cq.y * Gj + Pi * Gbar);
-                    atomicAdd(&acc[0][s], -sc_ * xx);
-                    atomicAdd(&acc[1][s], -sc_ * xy);
-                    atomicAdd(&acc[2][s], -sc_ * xz);
-                    atomicAdd(&acc[3][s], mj * Gi * vdotx);
-                    atomicAdd(&acc[4][s], mj * Pi * Gbar * vdotx);
-                    if (mu < R(0)) atomicMax(&amu[s], -mu);
+                    if (valid) {
+                        atomicAdd(&acc[0][s], -sc_ * xx);
+                        atomicAdd(&acc[1][s], -sc_ * xy);
+                        atomicAdd(&acc[2][s], -sc_ * xz);
+                        atomicAdd(&acc[3][s], mj * Gi * vdotx);
+                        atomicAdd(&acc[4][s], mj * Pi * Gbar * vdotx);
+                        if (mu < R(0)) atomicMax(&amu[s], -mu);
+                    }
                 });
             };
             if (MIXED && wrapf) tile(std::true_type{});

@@ -52,7 +52,7 @@ def cloud(case):
 
 @pytest.mark.parametrize("case", CLOUDS, ids=lambda c: f"n{c['n']}-{c['kernel']}")
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("bucket", [16, 32, 64])
+@pytest.mark.parametrize("bucket", [8, 16, 32, 64])
 def test_neighbor_sets_bit_exact(sph, orc, case, mode, bucket):
     c = cloud(case)
     s, p = c["state"], c["params"]
