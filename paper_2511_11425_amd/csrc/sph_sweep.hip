@@ -440,33 +440,50 @@ template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 // A staged tile holds 64 candidates; a wave holds 64 sinks.  Evaluating the
 // full 64 x 64 block with one sink per lane executes the interaction maths for
 // every candidate that ANY lane accepts, i.e. for nearly all of them, while
-// only ~15% of the (sink, candidate) pairs are neighbours.  The sweep
-// therefore runs two phases per tile:
-//   test     lane = sink, candidates by LDS broadcast, distance test only;
-//            the accepted pairs are compacted into an LDS pair list in rounds:
-//            round r holds the r-th accepted candidate of every lane that has
-//            one, so entries of a round have distinct sinks;
-//   interact lane = pair: 64 accepted pairs per step, contributions added to
-//            the sink's LDS accumulator with LDS float atomics (one wave per
-//            workgroup, so the order of the adds is fixed).
+// only ~10% of the (sink, candidate) pairs are neighbours.  The sweep
+// therefore separates, per tile:
+//   test     lane = sink, candidates by LDS broadcast, distance test only,
+//            giving a 64-bit hit mask per lane;
+//   compact  in rounds: round r appends the r-th accepted candidate of every
+//            lane that has one to a small LDS ring of pairs (so entries of a
+//            round have distinct sinks), and the rounds stop after as many as
+//            the largest per-lane count, typically far fewer than 64;
+//   interact lane = pair: whenever U x 64 pairs are pending, they are
+//            fetched together (their LDS latencies overlap) and their
+//            contributions added to the sinks' LDS accumulators with LDS
+//            float atomics (one wave per workgroup, so the order of the adds
+//            is fixed).  The remainder is drained at the end of the tile.
 // Each sink then folds the tile's partial sums into its own accumulators.
+// The ring never holds more than U x 64 - 1 + 64 pairs, so the pair list
+// costs kRing x 2 bytes of LDS instead of one entry per possible pair.
+constexpr int kRing = 256;
 
-// Pass 1 only reads LDS (the distance tests, so the reads of all 64 staged
-// candidates can be in flight together) and keeps a 64-bit hit mask per lane;
-// pass 2 takes one accepted candidate per lane and round (lowest set bit) and
-// stops after as many rounds as the largest per-lane count, typically far
-// fewer than 64.
-constexpr int kPairCap = kWave * kWave;
-
-// `hit8(k0)` returns the accepted bits of candidates k0..k0+7 of this lane.
-template <class Hit8>
-__device__ __forceinline__ int compact_tile(uint16_t *pairs, Hit8 hit8, int &hits) {
+// `hit8(k0)` returns the accepted bits of candidates k0..k0+7 of this lane;
+// `fetch(s, k)` loads the operands of pair (sink s, candidate k) and
+// `apply(d, valid)` adds its contributions when `valid`.
+template <int U, class Hit8, class Fetch, class Apply>
+__device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetch, Apply apply,
+                                           int &hits) {
+    static_assert(U * kWave + kWave <= kRing, "pair ring too small");
     const int lane = threadIdx.x;
     uint64_t m = 0;
 #pragma unroll 2
     for (int k0 = 0; k0 < kWave; k0 += 8) m |= (uint64_t)hit8(k0) << k0;
     hits += __popcll(m);
-    int base = 0;
+    int produced = 0, consumed = 0;
+    auto run = [&](int n) {   // pairs consumed .. consumed + n - 1, n <= U * 64
+        decltype(fetch(0, 0)) d[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = u * kWave + lane;
+            const uint16_t p = ring[(consumed + (t < n ? t : 0)) & (kRing - 1)];
+            d[u] = fetch((int)(p >> 6), (int)(p & 63));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (u == 0 || u * kWave < n) apply(d[u], u * kWave + lane < n);
+        consumed += n;
+    };
     for (;;) {
         const bool h = m != 0ull;
         const uint64_t bal = __ballot(h);
@@ -474,32 +491,18 @@ __device__ __forceinline__ int compact_tile(uint16_t *pairs, Hit8 hit8, int &hit
         if (h) {
             const int below = (int)__builtin_amdgcn_mbcnt_hi(
                 (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            pairs[base + below] = (uint16_t)((lane << 6) | __builtin_ctzll(m));
+            ring[(produced + below) & (kRing - 1)] = (uint16_t)((lane << 6) | __builtin_ctzll(m));
             m &= m - 1ull;
         }
-        base += __popcll(bal);
-    }
-    return base;
-}
-
-// Interaction phase: U chunks of 64 pairs per step, all operands of the U
-// pairs fetched from LDS before any is used (so their latencies overlap).
-// Lanes past the end fetch pair 0 and apply nothing.
-template <int U, class Fetch, class Apply>
-__device__ __forceinline__ void for_pairs(const uint16_t *pairs, int T, Fetch fetch, Apply apply) {
-    const int lane = threadIdx.x;
-    for (int c = 0; c < T; c += U * kWave) {
-        decltype(fetch(0, 0)) d[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = c + u * kWave + lane;
-            const uint16_t p = pairs[t < T ? t : 0];
-            d[u] = fetch((int)(p >> 6), (int)(p & 63));
+        produced += __popcll(bal);
+        if (produced - consumed >= U * kWave) {
+            __syncthreads();
+            run(U * kWave);
+            __syncthreads();
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (u == 0 || c + u * kWave < T) apply(d[u], c + u * kWave + lane < T);
     }
+    __syncthreads();
+    while (produced > consumed) run(min(U * kWave, produced - consumed));
 }
 
 // Four consecutive entries of an LDS array (one 128-bit read for FP32).
@@ -541,12 +544,14 @@ __device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool pe
 
 // ================================================================ density
 
+// The mixed density kernel is held to 168 VGPRs (three waves per SIMD; its LDS
+// allows more): latency hiding pays more than the few values it spills.
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 2))) void k_density(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
-    __shared__ uint16_t pairs[kPairCap + kWave];
+    __shared__ uint16_t ring[kRing];
     __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], tm[kWave];  // candidates
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
     __shared__ R acc0[kWave], acc1[kWave], acc2[kWave];
@@ -683,7 +688,8 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                         return pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
                                                        dx, dy, dz) < H2 ? 1u : 0u;
                     };
-                    const int T = compact_tile(pairs, [&](int k0) {
+                    struct PD { int s; R x, y, z, m; V4<R> si; };
+                    tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0) {
                         uint32_t b = 0;
 #pragma unroll
                         for (int h = 0; h < 8; h += 4) {
@@ -693,10 +699,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                                   in(X.z, Y.z, Z.z) << 2 | in(X.w, Y.w, Z.w) << 3) << h;
                         }
                         return b;
-                    }, cnt);
-                    __syncthreads();
-                    struct PD { int s; R x, y, z, m; V4<R> si; };
-                    for_pairs<MIXED ? 2 : 1>(pairs, T, [&](int s, int k) {
+                    }, [&](int s, int k) {
                         return PD{s, tx[k], ty[k], tz[k], tm[k], sp[s]};
                     }, [&](const PD &d, bool valid) {
                         R ex, ey, ez;
@@ -710,7 +713,7 @@ __global__ __launch_bounds__(kWave) void k_density(SweepArgs a) {
                             atomicAdd(&acc1[d.s], d.m * t1);
                             atomicAdd(&acc2[d.s], d.m * t2);
                         }
-                    });
+                    }, cnt);
                 };
                 if (MIXED && wrapf) tile(std::true_type{});
                 else tile(std::false_type{});
@@ -822,7 +825,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
-    __shared__ uint16_t pairs[kPairCap + kWave];
+    __shared__ uint16_t ring[kRing];
     // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho)
     __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], th2[kWave], tm[kWave];
     __shared__ V4<R> tv[kWave], tq[kWave];
@@ -946,7 +949,8 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                     return (inside && r2 > R(0)) ? 1u : 0u;
                 };
                 int interacting = 0;
-                const int T = compact_tile(pairs, [&](int k0) {
+                struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
+                tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0) {
                     uint32_t b = 0, nb = 0;
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
@@ -958,10 +962,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                     }
                     cnt += (int)nb;
                     return b;
-                }, interacting);
-                __syncthreads();
-                struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
-                for_pairs<MIXED ? 2 : 1>(pairs, T, [&](int s, int k) {
+                }, [&](int s, int k) {
                     return PF{s, tx[k], ty[k], tz[k], tm[k], tv[k], tq[k], sp[s], sv[s], sq[s]};
                 }, [&](const PF &d, bool valid) {
                     const int s = d.s;
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                         atomicAdd(&acc[4][s], mj * Pi * Gbar * vdotx);
                         if (mu < R(0)) atomicMax(&amu[s], -mu);
                     }
-                });
+                }, interacting);
             };
             if (MIXED && wrapf) tile(std::true_type{});
             else tile(std::false_type{});
