@@ -16,7 +16,7 @@ namespace sphmi {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kGroup = 64;         // sink group: one wavefront, one particle per lane
 constexpr int kStackCap = 1024;    // per-wave walk stack (node ids) in LDS
-constexpr int kCandCap = 512;      // per-wave candidate-bucket list in LDS
+constexpr int kCandCap = 256;      // per-wave candidate-bucket list in LDS
 constexpr int kMaxRow = 4096;      // longest neighbour row sph_neighbors can sort
 
 // Device counters of the most recent call (all 64-bit, summed with integer

@@ -455,7 +455,10 @@ template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 //            is fixed).  The remainder is drained at the end of the tile.
 // Each sink then folds the tile's partial sums into its own accumulators.
 // The ring never holds more than U x 64 - 1 + 64 pairs, so the pair list
-// costs kRing x 2 bytes of LDS instead of one entry per possible pair.
+// costs kRing x 2 bytes of LDS instead of one entry per possible pair.  The
+// workgroup is one wave, whose LDS instructions execute in issue order, so
+// ring writes and reads need only a compiler-level ordering point (a
+// workgroup barrier would also wait for every outstanding LDS atomic).
 constexpr int kRing = 256;
 
 // `hit8(k0)` returns the accepted bits of candidates k0..k0+7 of this lane;
@@ -496,12 +499,12 @@ __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetc
         }
         produced += __popcll(bal);
         if (produced - consumed >= U * kWave) {
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
             run(U * kWave);
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     while (produced > consumed) run(min(U * kWave, produced - consumed));
 }
 
@@ -515,11 +518,11 @@ __device__ __forceinline__ float pair_sqrt(float x) { return __builtin_amdgcn_sq
 __device__ __forceinline__ double pair_sqrt(double x) { return sqrt(x); }
 
 // Pair difference d = x_k - x_i (candidate minus sink).  FP64: absolute
-// coordinates, minimum image, distance without contraction (the sets are
-// bit-exact).  Mixed: FP32 coordinates relative to the group centre,
-// re-wrapped only when the group is too wide for the single image chosen at
-// staging; r^2 with fused multiply-adds (the same expression for the test and
-// the interaction, and symmetric in i and j).
+// coordinates, minimum image in tiles that may need it (WRAP), distance
+// without contraction (the sets are bit-exact).  Mixed: FP32 coordinates
+// relative to the group centre, re-wrapped (WRAP) only when the group is too
+// wide for the single image chosen at staging; r^2 with fused multiply-adds
+// (the same expression for the test and the interaction, symmetric in i, j).
 template <bool MIXED, bool WRAP, typename R>
 __device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool per,
                                      const SetGeom &g, const R *Lf, const R *hLf,
@@ -533,13 +536,25 @@ __device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool pe
         }
         return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     } else {
-        if (per) {
+        if (WRAP && per) {
             dx = min_image(dx, g.L[0], g.halfL[0]);
             dy = min_image(dy, g.L[1], g.halfL[1]);
             dz = min_image(dz, g.L[2], g.halfL[2]);
         }
         return r2_exact(dx, dy, dz);
     }
+}
+
+// FP64 tiles: the minimum image is the identity for every pair of the tile
+// when each candidate lies within half a box minus the group's extent of the
+// group centre on every axis (|x_j - x_i| <= |x_j - gc| + |gc - x_i|), so such
+// tiles skip it and keep bit-identical distances.
+__device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const double *gc,
+                                            const double *gext, double x, double y, double z) {
+    if (!per) return false;
+    return fabs(x - gc[0]) + gext[0] >= 0.999 * g.halfL[0] ||
+           fabs(y - gc[1]) + gext[1] >= 0.999 * g.halfL[1] ||
+           fabs(z - gc[2]) + gext[2] >= 0.999 * g.halfL[2];
 }
 
 // ================================================================ density
@@ -663,6 +678,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             }
             for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
                 int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+                bool far = false;
                 if (j >= 0) {
                     const R mj = (R)a.ms[j];
                     if constexpr (MIXED) {
@@ -675,10 +691,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                         tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2; tm[lane] = mj;
                     } else {
                         tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j]; tm[lane] = mj;
+                        far = needs_image(per, g, gc, gext, a.xs[j], a.ys[j], a.zs[j]);
                     }
                 } else {
                     tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
                 }
+                if constexpr (!MIXED) wrapf = __any(far);
                 cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
                 __syncthreads();
                 auto tile = [&](auto wrap_tag) {
@@ -715,7 +733,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                         }
                     }, cnt);
                 };
-                if (MIXED && wrapf) tile(std::true_type{});
+                if (wrapf) tile(std::true_type{});
                 else tile(std::false_type{});
                 __syncthreads();
                 const R p0 = acc0[lane], p1 = acc1[lane], p2 = acc2[lane];
@@ -761,11 +779,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             const double newton = dF > 0.0 ? F / dF : NAN;
             const double den = 2.0 * dF * dF - F * d2F;
             const double step = (dF > 0.0 && den > 0.0) ? 2.0 * F * dF / den : newton;
+            // a small Halley step is taken without another scan: it leaves an
+            // O((step/H)^3) error in H and, through the second-order Taylor
+            // step of S0, in rho; Omega's first-order step of T1 leaves
+            // O((step/H)^2), so FP64 accepts steps up to sqrt(tol) H
+            const double accept = MIXED ? 2e-3 : sqrt(a.tol);
             if (F == 0.0 || (!MIXED && fabs(newton) <= a.tol * H)) {
                 done = true;
-            } else if (MIXED && fabs(step) <= 2e-3 * H) {
-                // one Halley step leaves O((step/H)^3) error; the sums at the new
-                // H follow from their derivatives (S0'' = T2/H^2, T1' = -(T2-T1)/H)
+            } else if (fabs(step) <= accept * H && H - step <= cap) {
+                // the sums at the new H follow from their derivatives
+                // (S0'' = T2/H^2, T1' = -(T2-T1)/H)
                 done = true;
                 const double dH = -step;
                 const double S0n = S0 - T1 / H * dH + 0.5 * T2 / (H * H) * dH * dH;
@@ -820,8 +843,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
 
 // ================================================================ forces
 
+// The mixed force kernel is held to three waves per SIMD as well; it spills a
+// few long-lived values to scratch, which costs less than the lost latency
+// hiding at two waves.
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 2))) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
@@ -904,6 +930,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
         refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, ws);
         for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
             int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+            bool far = false;
             if (j >= 0) {
                 const R mj = (R)a.ms[j];
                 if constexpr (MIXED) {
@@ -916,6 +943,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                     tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
                 } else {
                     tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
+                    far = needs_image(per, g, gc, gext, a.xs[j], a.ys[j], a.zs[j]);
                 }
                 tm[lane] = mj;
                 const double Hj = a.Hs[j];
@@ -934,6 +962,8 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
             if constexpr (MIXED) {
                 double reach = fmax(Hsink_max, wave_max(j >= 0 ? a.Hs[j] : 0.0));
                 wrapf = group_needs_wrap(per, g, gext, reach);
+            } else {
+                wrapf = __any(far);
             }
             __syncthreads();
             auto tile = [&](auto wrap_tag) {
@@ -1008,7 +1038,7 @@ __global__ __launch_bounds__(kWave) void k_forces(SweepArgs a) {
                     }
                 }, interacting);
             };
-            if (MIXED && wrapf) tile(std::true_type{});
+            if (wrapf) tile(std::true_type{});
             else tile(std::false_type{});
             __syncthreads();
             for (int q = 0; q < 5; ++q) {
