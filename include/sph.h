@@ -70,9 +70,10 @@ typedef struct {
     int32_t kernel;    /* SPH_KERNEL_*: cubic spline (Monaghan 1992) or Wendland C2/C4/C6
                           (Dehnen & Aly 2012), Sec. 2.3.  Default M4. */
     int32_t precision; /* SPH_PREC_FP64: all pair arithmetic in FP64.
-                          SPH_PREC_MIXED: pair arithmetic in FP32 on bucket-relative
-                          coordinates with compensated sums; positions, the step and
-                          the global reductions stay FP64.  Default FP64. */
+                          SPH_PREC_MIXED: pair arithmetic in FP32 on coordinates
+                          relative to the sink group, the pair terms summed in FP64;
+                          positions, the step and the global reductions stay FP64.
+                          Default FP64. */
     int32_t eos;       /* SPH_EOS_IDEAL: P = (gamma-1) rho u (Sec. 2.3.1).
                           SPH_EOS_STIFFENED: P = (gamma-1) rho u - gamma P0. */
     int32_t periodic;  /* 1: periodic box [box_lo, box_hi) with minimum image;

@@ -24,9 +24,8 @@
 // evaluated as (dx*dx + dy*dy) + dz*dz without contraction, so neighbour
 // sets are reproducible bit for bit.  Mixed path = pair arithmetic in FP32 on
 // coordinates relative to the sink group's centre (formed in FP64, rounded
-// once per staged candidate), per-tile FP32 partial sums folded into
-// Neumaier-compensated FP32 accumulators; H iteration bookkeeping, positions
-// and outputs stay FP64.
+// once per staged candidate); the FP32 pair terms are summed in FP64 per
+// sink; H iteration bookkeeping, positions and outputs stay FP64.
 #include "sph_internal.h"
 
 #include <cfloat>
@@ -379,12 +378,21 @@ __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__re
     __syncthreads();
 }
 
-// Neumaier-compensated accumulation (FP32 partial sums of the mixed path).
-__device__ __forceinline__ void neumaier(float &sum, float &comp, float v) {
-    float t = sum + v;
-    if (fabsf(sum) >= fabsf(v)) comp += (sum - t) + v;
-    else comp += (v - t) + sum;
-    sum = t;
+// Per-sink sums are accumulated in FP64 in both paths: the pair terms of the
+// mixed path are FP32, their sum is not.  (LDS atomic adds are native for
+// FP64 on gfx950; the FP32 form was measured several times slower, and a
+// wider accumulator also replaces a compensated FP32 sum.)  The largest
+// signal term is a maximum of non-negative values, kept as the integer
+// maximum of their bit patterns.
+__device__ __forceinline__ void lds_max_nonneg(uint32_t *p, float v) {
+    atomicMax(p, __float_as_uint(v));
+}
+__device__ __forceinline__ void lds_max_nonneg(unsigned long long *p, double v) {
+    atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ float bits_to_real(uint32_t b) { return __uint_as_float(b); }
+__device__ __forceinline__ double bits_to_real(unsigned long long b) {
+    return __longlong_as_double((long long)b);
 }
 
 struct SweepArgs {
@@ -470,7 +478,7 @@ __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetc
     static_assert(U * kWave + kWave <= kRing, "pair ring too small");
     const int lane = threadIdx.x;
     uint64_t m = 0;
-#pragma unroll 2
+#pragma unroll 1
     for (int k0 = 0; k0 < kWave; k0 += 8) m |= (uint64_t)hit8(k0) << k0;
     hits += __popcll(m);
     int produced = 0, consumed = 0;
@@ -569,7 +577,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     __shared__ uint16_t ring[kRing];
     __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], tm[kWave];  // candidates
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
-    __shared__ R acc0[kWave], acc1[kWave], acc2[kWave];
+    __shared__ double acc0[kWave], acc1[kWave], acc2[kWave];
 
     const int lane = threadIdx.x;
     const int64_t grp = blockIdx.x;
@@ -648,7 +656,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
         // particle meets itself (r = 0: f = 1, q f' = 0), which is the self
         // term of the density; it is not counted as a neighbour.
         double S0 = 0.0, T1 = 0.0, T2 = 0.0;
-        float c0s = 0.f, c0c = 0.f, c1s = 0.f, c1c = 0.f, c2s = 0.f, c2c = 0.f;
         int cnt = 0;
         const R Hr = (R)H;
         const R Hinv = R(1) / Hr;
@@ -669,7 +676,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     ++overflows;
                     linear = true;
                     S0 = T1 = T2 = 0.0;
-                    c0s = c0c = c1s = c1c = c2s = c2c = 0.f;
                     cnt = 0;
                     first_chunk = true;
                     continue;
@@ -727,34 +733,22 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                         R f, t1, t2;
                         shape_f_t1_t2<K, R>(q, f, t1, t2);
                         if (valid) {
-                            atomicAdd(&acc0[d.s], d.m * f);
-                            atomicAdd(&acc1[d.s], d.m * t1);
-                            atomicAdd(&acc2[d.s], d.m * t2);
+                            atomicAdd(&acc0[d.s], (double)(d.m * f));
+                            atomicAdd(&acc1[d.s], (double)(d.m * t1));
+                            atomicAdd(&acc2[d.s], (double)(d.m * t2));
                         }
                     }, cnt);
                 };
                 if (wrapf) tile(std::true_type{});
                 else tile(std::false_type{});
                 __syncthreads();
-                const R p0 = acc0[lane], p1 = acc1[lane], p2 = acc2[lane];
+                S0 += acc0[lane];
+                T1 += acc1[lane];
+                T2 += acc2[lane];
                 acc0[lane] = 0; acc1[lane] = 0; acc2[lane] = 0;
-                if constexpr (MIXED) {
-                    neumaier(c0s, c0c, p0);
-                    neumaier(c1s, c1c, p1);
-                    neumaier(c2s, c2c, p2);
-                } else {
-                    S0 += p0;
-                    T1 += p1;
-                    T2 += p2;
-                }
             }
             first_chunk = false;
             if (ws.nstack == 0) break;  // walk finished
-        }
-        if constexpr (MIXED) {
-            S0 = (double)c0s + (double)c0c;
-            T1 = (double)c1s + (double)c1c;
-            T2 = (double)c2s + (double)c2c;
         }
         ++scans;
         // ---- Halley update per lane, safeguarded by a bracket (Sec. 2.3.3:
@@ -856,8 +850,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], th2[kWave], tm[kWave];
     __shared__ V4<R> tv[kWave], tq[kWave];
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
-    __shared__ R acc[5][kWave];
-    __shared__ R amu[kWave];
+    typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
+    __shared__ double acc[5][kWave];
+    __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
 
     const int lane = threadIdx.x;
     const int64_t grp = blockIdx.x;
@@ -909,7 +904,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     int overflows = 0;
 
     double acc_d[5] = {0, 0, 0, 0, 0};
-    float acc_s[5] = {0, 0, 0, 0, 0}, acc_c[5] = {0, 0, 0, 0, 0};
     int cnt = 0;
     unsigned long long cand_tested = 0;
     walk_reset(stack, ws, linear);
@@ -920,7 +914,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             // restart the whole pass with the linear bucket test
             ++overflows;
             linear = true;
-            for (int q = 0; q < 5; ++q) { acc_d[q] = 0; acc_s[q] = 0; acc_c[q] = 0; }
+            for (int q = 0; q < 5; ++q) acc_d[q] = 0;
             cnt = 0;
             cand_tested = 0;
             amu[lane] = 0;
@@ -980,7 +974,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                 };
                 int interacting = 0;
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
-                tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0) {
+                tile_pairs<1>(ring, [&](int k0) {
                     uint32_t b = 0, nb = 0;
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
@@ -1029,12 +1023,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     const R mj = d.m;
                     const R sc_ = mj * (iq.x * Gi + cq.y * Gj + Pi * Gbar);
                     if (valid) {
-                        atomicAdd(&acc[0][s], -sc_ * xx);
-                        atomicAdd(&acc[1][s], -sc_ * xy);
-                        atomicAdd(&acc[2][s], -sc_ * xz);
-                        atomicAdd(&acc[3][s], mj * Gi * vdotx);
-                        atomicAdd(&acc[4][s], mj * Pi * Gbar * vdotx);
-                        if (mu < R(0)) atomicMax(&amu[s], -mu);
+                        atomicAdd(&acc[0][s], (double)(-sc_ * xx));
+                        atomicAdd(&acc[1][s], (double)(-sc_ * xy));
+                        atomicAdd(&acc[2][s], (double)(-sc_ * xz));
+                        atomicAdd(&acc[3][s], (double)(mj * Gi * vdotx));
+                        atomicAdd(&acc[4][s], (double)(mj * Pi * Gbar * vdotx));
+                        if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
                 }, interacting);
             };
@@ -1042,20 +1036,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             else tile(std::false_type{});
             __syncthreads();
             for (int q = 0; q < 5; ++q) {
-                const R v = acc[q][lane];
+                acc_d[q] += acc[q][lane];
                 acc[q][lane] = 0;
-                if constexpr (MIXED) neumaier(acc_s[q], acc_c[q], v);
-                else acc_d[q] += v;
             }
         }
         if (ws.nstack == 0) break;
         ws.ncand = 0;
     }
     __syncthreads();
-    const R mumax = amu[lane];
-    if constexpr (MIXED) {
-        for (int q = 0; q < 5; ++q) acc_d[q] = (double)acc_s[q] + (double)acc_c[q];
-    }
+    const R mumax = bits_to_real(amu[lane]);
     if (act) {
         const double axv = acc_d[0], ayv = acc_d[1], azv = acc_d[2];
         a.ax[i] = axv;
