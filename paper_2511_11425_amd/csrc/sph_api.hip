@@ -171,8 +171,6 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.vxs, n); A(c.vys, n); A(c.vzs, n); A(c.us, n);
     A(c.rhos, n); A(c.oms, n); A(c.As, n); A(c.css, n); A(c.Ps, n);
     A(c.axs, n); A(c.ays, n); A(c.azs, n); A(c.dus, n); A(c.dts, n);
-    A(c.fxs, n); A(c.fys, n); A(c.fzs, n);
-    A(c.bref, 3 * std::max<int64_t>(c.nbuckets, 1));
     A(c.nodes, c.nnodes);
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
     A(c.d_scan_tmp, c.scan_tmp_len);

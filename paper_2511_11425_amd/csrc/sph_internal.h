@@ -102,8 +102,6 @@ struct Ctx {
     double *rhos = nullptr, *oms = nullptr, *As = nullptr, *css = nullptr, *Ps = nullptr;
     double *axs = nullptr, *ays = nullptr, *azs = nullptr, *dus = nullptr, *dts = nullptr;
     // FP32 bucket-relative offsets for the mixed path
-    float *fxs = nullptr, *fys = nullptr, *fzs = nullptr;
-    double *bref = nullptr;         // per bucket: reference point (3 doubles)
 
     Node *nodes = nullptr;
 

@@ -95,20 +95,39 @@ __global__ void k_fill_f64(double *p, int n, double v) {
 }
 
 // Per-set minimum of dt (dt >= 0, so the bit patterns order like the values).
-__global__ void k_set_min_dt(const double *__restrict__ dt, int64_t n, const SetGeom *sets,
-                             int nsets, double *set_min) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = i < n;
-    int s = ok ? (nsets == 1 ? 0 : find_set_k(sets, nsets, i)) : 0;
-    double v = ok ? dt[i] : DBL_MAX;
-    int s0 = __shfl(s, 0);
-    bool uniform = __all(!ok || s == s0);
+// Per-set minimum of the particle steps.  A block reduces 2048 consecutive
+// particles; a block inside one set (the usual case) issues one atomic, a
+// block across a set boundary one per particle.
+constexpr int kMinItems = 8;
+
+__global__ __launch_bounds__(kThreads) void k_set_min_dt(const double *__restrict__ dt, int64_t n,
+                                                         const SetGeom *sets, int nsets,
+                                                         double *set_min) {
+    __shared__ double wmin[kThreads / 64];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kThreads * kMinItems;
+    const int64_t end = base + (int64_t)kThreads * kMinItems < n ? base + (int64_t)kThreads * kMinItems : n;
+    const int s0 = nsets == 1 ? 0 : find_set_k(sets, nsets, base);
+    const bool one_set = nsets == 1 || end <= sets[s0].p1;
     long long *dst = reinterpret_cast<long long *>(set_min);
-    if (uniform) {
+    if (one_set) {
+        double v = DBL_MAX;
+        for (int it = 0; it < kMinItems; ++it) {
+            const int64_t i = base + (int64_t)it * kThreads + tid;
+            if (i < end) v = fmin(v, dt[i]);
+        }
         for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-        if ((threadIdx.x & 63) == 0 && v < DBL_MAX) atomicMin(&dst[s0], dbits(v));
-    } else if (ok) {
-        atomicMin(&dst[s], dbits(v));
+        if ((tid & 63) == 0) wmin[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < kThreads / 64; ++w) v = fmin(v, wmin[w]);
+            if (v < DBL_MAX) atomicMin(&dst[s0], dbits(v));
+        }
+    } else {
+        for (int it = 0; it < kMinItems; ++it) {
+            const int64_t i = base + (int64_t)it * kThreads + tid;
+            if (i < end) atomicMin(&dst[find_set_k(sets, nsets, i)], dbits(dt[i]));
+        }
     }
 }
 
@@ -275,8 +294,8 @@ hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s) {
 hipError_t launch_set_dtnext(Ctx *c, const sph_particles *p, hipStream_t s) {
     k_fill_f64<<<nblk(c->nsets, 64), 64, 0, s>>>(c->d_set_dtnext, c->nsets, c->prm.dt_max);
     if (c->n > 0)
-        k_set_min_dt<<<nblk(c->n, kThreads), kThreads, 0, s>>>(p->dt, c->n, c->d_sets, c->nsets,
-                                                               c->d_set_dtnext);
+        k_set_min_dt<<<nblk(c->n, kThreads * kMinItems), kThreads, 0, s>>>(
+            p->dt, c->n, c->d_sets, c->nsets, c->d_set_dtnext);
     return hipGetLastError();
 }
 

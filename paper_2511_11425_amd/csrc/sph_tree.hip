@@ -322,41 +322,61 @@ __global__ void k_nodes_empty(Node *nodes, int64_t nn) {
 // One thread per bucket: cell bound, box-of-balls, ball-of-balls (centre at
 // the cell-bound centre), the bucket reference point and the FP32
 // bucket-relative offsets used by the mixed-precision path.
-__global__ void k_leaf_bounds(const SetGeom *__restrict__ sets, const int32_t *__restrict__ bkt_set,
-                              int64_t nbk, int B, const double *__restrict__ xs,
-                              const double *__restrict__ ys, const double *__restrict__ zs,
-                              const double *__restrict__ Hs, Node *__restrict__ nodes,
-                              double *__restrict__ bref, float *__restrict__ fx,
-                              float *__restrict__ fy, float *__restrict__ fz) {
-    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbk) return;
-    int s = bkt_set[b];
-    const SetGeom g = sets[s];
-    int64_t lb = b - g.b0;
-    int64_t p0 = g.p0 + lb * B;
-    int64_t p1 = p0 + B < g.p1 ? p0 + B : g.p1;
-    Node o;
-    node_empty(o);
-    for (int64_t k = p0; k < p1; ++k) {
-        double v[3] = {xs[k], ys[k], zs[k]};
-        double H = Hs[k];
+// Leaf bounds, one lane per particle: the B lanes of a bucket form an aligned
+// segment of the wave (B divides 64) and reduce the cell bound, the box of
+// the balls and the enclosing sphere with butterfly shuffles inside it.
+__global__ __launch_bounds__(256) void k_leaf_bounds(const SetGeom *__restrict__ sets,
+                                                     const int32_t *__restrict__ bkt_set,
+                                                     int64_t nbk, int B,
+                                                     const double *__restrict__ xs,
+                                                     const double *__restrict__ ys,
+                                                     const double *__restrict__ zs,
+                                                     const double *__restrict__ Hs,
+                                                     Node *__restrict__ nodes) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t b = t / B;
+    const int off = (int)(t - b * B);
+    const bool inb = b < nbk;
+    const int s = inb ? bkt_set[b] : 0;
+    const SetGeom &g = sets[s];
+    const int64_t lb = b - g.b0;
+    const int64_t k = g.p0 + lb * B + off;
+    const bool act = inb && k < g.p1;
+    double v[3] = {0.0, 0.0, 0.0}, H = 0.0;
+    if (act) { v[0] = xs[k]; v[1] = ys[k]; v[2] = zs[k]; H = Hs[k]; }
+    double clo[3], chi[3], blo[3], bhi[3];
+    for (int a = 0; a < 3; ++a) {
+        clo[a] = act ? v[a] : DBL_MAX;
+        chi[a] = act ? v[a] : -DBL_MAX;
+        blo[a] = act ? v[a] - H : DBL_MAX;
+        bhi[a] = act ? v[a] + H : -DBL_MAX;
+    }
+    for (int o = 1; o < B; o <<= 1) {
         for (int a = 0; a < 3; ++a) {
-            o.clo[a] = fmin(o.clo[a], v[a]); o.chi[a] = fmax(o.chi[a], v[a]);
-            o.blo[a] = fmin(o.blo[a], v[a] - H); o.bhi[a] = fmax(o.bhi[a], v[a] + H);
+            clo[a] = fmin(clo[a], __shfl_xor(clo[a], o));
+            chi[a] = fmax(chi[a], __shfl_xor(chi[a], o));
+            blo[a] = fmin(blo[a], __shfl_xor(blo[a], o));
+            bhi[a] = fmax(bhi[a], __shfl_xor(bhi[a], o));
         }
     }
-    double c[3], R = 0.0;
-    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (o.clo[a] + o.chi[a]);
-    for (int64_t k = p0; k < p1; ++k) {
-        double dx = xs[k] - c[0], dy = ys[k] - c[1], dz = zs[k] - c[2];
-        double r = sqrt(dx * dx + dy * dy + dz * dz) + Hs[k];
-        R = fmax(R, r);
-        fx[k] = (float)dx; fy[k] = (float)dy; fz[k] = (float)dz;
+    double c[3];
+    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (clo[a] + chi[a]);
+    double R = -1.0;
+    if (act) {
+        const double dx = v[0] - c[0], dy = v[1] - c[1], dz = v[2] - c[2];
+        R = sqrt(dx * dx + dy * dy + dz * dz) + H;
     }
-    for (int a = 0; a < 3; ++a) o.bc[a] = c[a];
-    o.br = p1 > p0 ? R * (1.0 + 1e-12) : -1.0;
-    bref[3 * b + 0] = c[0]; bref[3 * b + 1] = c[1]; bref[3 * b + 2] = c[2];
-    nodes[g.node0 + g.nbp + lb] = o;
+    for (int o = 1; o < B; o <<= 1) R = fmax(R, __shfl_xor(R, o));
+    if (inb && off == 0) {
+        Node o;
+        for (int a = 0; a < 3; ++a) {
+            o.clo[a] = clo[a]; o.chi[a] = chi[a];
+            o.blo[a] = blo[a]; o.bhi[a] = bhi[a];
+            o.bc[a] = R >= 0.0 ? c[a] : 0.0;
+        }
+        o.br = R >= 0.0 ? R * (1.0 + 1e-12) : -1.0;
+        nodes[g.node0 + g.nbp + lb] = o;
+    }
 }
 
 // Smallest sphere enclosing two spheres (not required to be minimal for a
@@ -424,9 +444,8 @@ hipError_t launch_init_nodes(Ctx *c, hipStream_t s) {
 
 hipError_t launch_refit(Ctx *c, hipStream_t s) {
     if (c->nbuckets == 0) return hipSuccess;
-    k_leaf_bounds<<<nblk(c->nbuckets, 128), 128, 0, s>>>(c->d_sets, c->d_bkt_set, c->nbuckets,
-                                                         c->bucket, c->xs, c->ys, c->zs, c->Hs,
-                                                         c->nodes, c->bref, c->fxs, c->fys, c->fzs);
+    k_leaf_bounds<<<nblk(c->nbuckets * c->bucket, 256), 256, 0, s>>>(
+        c->d_sets, c->d_bkt_set, c->nbuckets, c->bucket, c->xs, c->ys, c->zs, c->Hs, c->nodes);
     for (int d = 1; d <= c->max_depth; ++d) {
         int64_t tot = c->level_total[d];
         if (tot <= 0) continue;
