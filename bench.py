@@ -40,6 +40,8 @@ if ROOT not in sys.path:
 FLOP_DENSITY_PAIR = 31
 FLOP_FORCE_PAIR = 84
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}   # MI355X vector peaks (FP32 figure is the packed one)
+PEAK_F32_UNPACKED = 78.6e12   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, without packed FP32
+KERNEL_INDEX = {"m4": 0, "wc2": 1, "wc4": 2, "wc6": 3}
 
 
 def _ngroups(sizes):
@@ -62,7 +64,8 @@ def make_workload(name, small=False):
         keys = b["sets"][0].keys()
         st = {k: np.concatenate([x[k] for x in b["sets"]]) for k in keys}
         offs = np.concatenate([[0], np.cumsum([len(x["x"]) for x in b["sets"]])]).tolist()
-        c = {"state": st, "params": b["params"], "set_offsets": offs,
+        c = {"state": st, "params": b["params"], "set_offsets": offs, "graph": True,
+             "autotune": True,
              "desc": f"{len(b['sets'])} independent periodic boxes of 4096-65536 particles, "
                      f"cubic spline, 64 neighbours"}
     elif name == "spheres":
@@ -87,53 +90,102 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(case, precision, steps, warmup):
+def run_gpu(case, precision, steps, warmup, graph=False):
+    """Warm up, then time `steps` full steps.  Kernel durations come from HIP
+    events the library records on its stream around each sweep kernel, read
+    after every timed step (the read synchronises, which the wall time of the
+    timed region includes).  With `graph`, one captured step is replayed and
+    timed by wall clock; kernel durations then come from the last three eager
+    warm-up steps."""
     import torch
     import paper_2511_11425_amd as sph
     p = dict(case["params"], precision=precision)
     P = sph.ParticleArrays.from_state(case["state"], device="cuda:0")
     ctx = sph.Context(p, set_offsets=case.get("set_offsets"))
     ctx.init(P)
-    for _ in range(warmup):
-        ctx.step(P)
-    torch.cuda.synchronize()
-    s0 = ctx.stats()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.step(P)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s1 = ctx.stats()
-    pairs = (s1["pairs_density_total"] - s0["pairs_density_total"]) + \
-            (s1["pairs_force_total"] - s0["pairs_force_total"])
-    wall = t1 - t0
-    # phase split with HIP events inside the library (separate, untimed above)
-    ctx.set_timing(True)
+    bucket = p.get("bucket", 32)
+    if case.get("autotune"):
+        bucket = ctx.autotune(P)
     tden, tfor, ttree, ttot = [], [], [], []
-    for _ in range(max(3, min(steps, 10))):
+    for w in range(warmup):
+        if graph and w >= warmup - 3:
+            # the replayed graph runs the same kernels: their durations are
+            # taken from the last eager warm-up steps
+            ctx.set_timing(True)
         ctx.step(P)
-        st = ctx.stats()
-        tden.append(st["t_density_ms"]); tfor.append(st["t_forces_ms"])
-        ttree.append(st["t_tree_ms"]); ttot.append(st["t_total_ms"])
+        if graph and w >= warmup - 3:
+            st = ctx.stats()
+            tden.append(st["t_density_ms"]); tfor.append(st["t_forces_ms"])
+            ttree.append(st["t_tree_ms"]); ttot.append(st["t_total_ms"])
     ctx.set_timing(False)
-    st = ctx.stats()
+    torch.cuda.synchronize()
+    if graph:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            ctx.graph_capture_step(P, 0.0, stream=stream)
+        torch.cuda.synchronize()
+        s0 = ctx.stats()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                ctx.graph_launch(stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = ctx.stats()
+    else:
+        ctx.set_timing(True)
+        s0 = ctx.stats()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.step(P)
+            st = ctx.stats()
+            tden.append(st["t_density_ms"]); tfor.append(st["t_forces_ms"])
+            ttree.append(st["t_tree_ms"]); ttot.append(st["t_total_ms"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.set_timing(False)
+    pairs = (st["pairs_density_total"] - s0["pairs_density_total"]) + \
+            (st["pairs_force_total"] - s0["pairs_force_total"])
+    wall = t1 - t0
     res = {
-        "precision": precision,
+        "precision": precision, "bucket": bucket, "graph": graph,
         "pairs_per_s": pairs / wall,
         "ms_per_step": 1e3 * wall / steps,
         "pairs_density": st["pairs_density"], "pairs_force": st["pairs_force"],
         "cand_density": st["cand_density"], "cand_force": st["cand_force"],
         "nr_scans_mean": st["nr_scans"] / max(1, case["ngroups"]),
         "nr_iter_max": st["nr_iter_max"], "n_noconv": st["n_noconv"],
-        "t_density_ms": float(np.median(tden)), "t_forces_ms": float(np.median(tfor)),
-        "t_tree_ms": float(np.median(ttree)), "t_step_ms": float(np.median(ttot)),
+        "n_overflow": st["n_overflow"],
     }
-    res["metric_rate"] = (st["pairs_density"] + st["pairs_force"]) / \
-        (1e-3 * (res["t_density_ms"] + res["t_forces_ms"]))
+    if tden:
+        res.update({"t_density_ms": float(np.mean(tden)), "t_forces_ms": float(np.mean(tfor)),
+                    "t_tree_ms": float(np.mean(ttree)), "t_step_ms": float(np.mean(ttot))})
+        res["metric_rate"] = (st["pairs_density"] + st["pairs_force"]) / \
+            (1e-3 * (res["t_density_ms"] + res["t_forces_ms"]))
     ctx.close()
     del P
     torch.cuda.empty_cache()
     return res
+
+
+def traffic_of(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when that summary was taken on a different kernel source or workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("workload") != workload:
+        return None
+    src = os.path.join(ROOT, "paper_2511_11425_amd", "csrc", "sph_sweep.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def cpu_baseline(case, seconds=15.0):
@@ -191,6 +243,7 @@ def main():
     ap.add_argument("--small", action="store_true", help="64^3 instead of 128^3 (quick check)")
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--workload", default="large", choices=list(WORKLOADS))
+    ap.add_argument("--graph", action="store_true", help="replay one captured step as a HIP graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 5 times (calibrates the HBM "
                          "FETCH_SIZE/WRITE_SIZE counters against a known byte count)")
@@ -210,24 +263,36 @@ def main():
         sys.exit(2)
     log(f"generating workload {args.workload}")
     case = make_workload(args.workload, args.small)
+    graph = args.graph or case.get("graph", False)
     results = {}
     for prec in args.precisions.split(","):
         log(f"timing {prec}")
-        results[prec] = run_gpu(case, prec, args.steps, args.warmup)
+        results[prec] = run_gpu(case, prec, args.steps, args.warmup, graph=graph)
         log(json.dumps(results[prec]))
     head = results.get("mixed") or results[next(iter(results))]
-    # roofline of the dominant kernel of the headline path
-    dom = "forces" if head["t_forces_ms"] >= head["t_density_ms"] else "density"
-    if dom == "forces":
-        flops = head["pairs_force"] * FLOP_FORCE_PAIR
-        t = head["t_forces_ms"] * 1e-3
-    else:
-        flops = head["pairs_density"] * FLOP_DENSITY_PAIR * head["nr_scans_mean"]
-        t = head["t_density_ms"] * 1e-3
-    dtype = "f32" if head["precision"] == "mixed" else "f64"
-    achieved = flops / t / 1e12
-    roof = {"bound": "alu", "kernel": f"k_{dom}", "achieved": achieved, "peak": PEAK[dtype] / 1e12,
-            "unit": "TFLOP/s", "frac": achieved * 1e12 / PEAK[dtype], "traffic": None}
+    mixed = head["precision"] == "mixed"
+    dtype = "f32" if mixed else "f64"
+    roof = None
+    if "t_forces_ms" in head:
+        # roofline of the dominant kernel of the headline path: algorithmic flops
+        # of one launch over its mean duration in the timed steps
+        dom = "forces" if head["t_forces_ms"] >= head["t_density_ms"] else "density"
+        if dom == "forces":
+            flops = head["pairs_force"] * FLOP_FORCE_PAIR
+            t = head["t_forces_ms"] * 1e-3
+        else:
+            flops = head["pairs_density"] * FLOP_DENSITY_PAIR * head["nr_scans_mean"]
+            t = head["t_density_ms"] * 1e-3
+        kidx = KERNEL_INDEX[case["params"].get("kernel", "m4")]
+        kname = f"k_{dom}<{kidx}, {'true' if mixed else 'false'}>"
+        achieved = flops / t
+        roof = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
+                "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
+                "traffic": traffic_of(kname, args.workload if not args.small else None),
+                "launch_ms": t * 1e3, "flops_per_launch": flops}
+        if mixed:
+            roof["peak_unpacked"] = PEAK_F32_UNPACKED / 1e12
+            roof["frac_unpacked"] = achieved / PEAK_F32_UNPACKED
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
@@ -241,16 +306,21 @@ def main():
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": case["desc"] + ", full KDK step, mixed precision",
-                   "particles": case["n"], "parallelism": "single GPU"},
-        "fp64": {k: results["fp64"][k] for k in ("pairs_per_s", "ms_per_step", "metric_rate")}
+        "config": {"workload": case["desc"] + ", full KDK step" +
+                   (", mixed precision" if mixed else ", FP64") +
+                   (", replayed HIP graph" if graph else ""),
+                   "particles": case["n"], "bucket": head["bucket"],
+                   "parallelism": "single GPU"},
+        "fp64": {k: results["fp64"].get(k) for k in ("pairs_per_s", "ms_per_step", "metric_rate",
+                                                     "t_density_ms", "t_forces_ms")}
         if "fp64" in results else None,
         "mixed_vs_fp64": (results["mixed"]["pairs_per_s"] / results["fp64"]["pairs_per_s"])
         if "mixed" in results and "fp64" in results else None,
-        "metric_rate_density_force_only": head["metric_rate"],
-        "phases_ms": {k: head[k] for k in ("t_tree_ms", "t_density_ms", "t_forces_ms", "t_step_ms")},
+        "metric_rate_density_force_only": head.get("metric_rate"),
+        "phases_ms": {k: head.get(k) for k in ("t_tree_ms", "t_density_ms", "t_forces_ms",
+                                               "t_step_ms")},
         "pairs": {k: head[k] for k in ("pairs_density", "pairs_force", "cand_density",
-                                       "cand_force", "nr_scans_mean")},
+                                       "cand_force", "nr_scans_mean", "n_overflow")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

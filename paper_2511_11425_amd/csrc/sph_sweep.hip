@@ -395,6 +395,18 @@ __device__ __forceinline__ double bits_to_real(unsigned long long b) {
     return __longlong_as_double((long long)b);
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD b mod
+// 8), and each XCD has its own L2.  Sink groups are numbered along the
+// Hilbert curve, so neighbouring groups share most of their candidates; this
+// permutation gives every XCD one contiguous range of groups, so those shared
+// candidates are fetched into one L2 instead of eight.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t n) {
+    const int64_t q = n / kXcds, r = n % kXcds;
+    const int64_t x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 struct SweepArgs {
     const SetGeom *sets;
     const int32_t *grp_set;
@@ -580,7 +592,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     __shared__ double acc0[kWave], acc1[kWave], acc2[kWave];
 
     const int lane = threadIdx.x;
-    const int64_t grp = blockIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
@@ -855,7 +867,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
 
     const int lane = threadIdx.x;
-    const int64_t grp = blockIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
@@ -1079,7 +1091,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
     __shared__ int32_t tid[kWave];
 
     const int lane = threadIdx.x;
-    const int64_t grp = blockIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;

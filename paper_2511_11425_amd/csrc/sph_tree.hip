@@ -89,32 +89,57 @@ __global__ void k_bbox_init(long long *enc, int nsets) {
 }
 
 // Open boundary: the key box of each set is the bounding box of its particles.
-__global__ void k_bbox(const double *__restrict__ x, const double *__restrict__ y,
-                       const double *__restrict__ z, int64_t n, const SetGeom *sets, int nsets,
-                       long long *enc) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = i < n;
-    int s = ok ? find_set(sets, nsets, i) : 0;
-    double v[3] = {ok ? x[i] : 0.0, ok ? y[i] : 0.0, ok ? z[i] : 0.0};
-    int s0 = __shfl(s, 0);
-    bool uniform = __all(!ok || s == s0);
-    bool anyok = __any(ok);
-    if (uniform) {
-        for (int a = 0; a < 3; ++a) {
-            double mn = ok ? v[a] : DBL_MAX, mx = ok ? v[a] : -DBL_MAX;
-            for (int o = 32; o > 0; o >>= 1) {
-                mn = fmin(mn, __shfl_xor(mn, o));
-                mx = fmax(mx, __shfl_xor(mx, o));
-            }
-            if ((threadIdx.x & 63) == 0 && anyok) {
-                atomicMin(&enc[s0 * 6 + a], dkey(mn));
-                atomicMax(&enc[s0 * 6 + 3 + a], dkey(mx));
+// A block reduces kBoxItems x 256 consecutive particles; a block inside one set
+// (the usual case) issues one atomic per bound, a block across a set boundary
+// one per particle and bound.
+constexpr int kBoxItems = 16;
+
+__global__ __launch_bounds__(256) void k_bbox(const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z, int64_t n,
+                                              const SetGeom *sets, int nsets, long long *enc) {
+    __shared__ double red[6][4];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * 256 * kBoxItems;
+    const int64_t end = base + 256 * kBoxItems < n ? base + 256 * kBoxItems : n;
+    const int s0 = nsets == 1 ? 0 : find_set(sets, nsets, base);
+    const bool one_set = nsets == 1 || end <= sets[s0].p1;
+    if (one_set) {
+        double mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+        for (int it = 0; it < kBoxItems; ++it) {
+            const int64_t i = base + (int64_t)it * 256 + tid;
+            if (i < end) {
+                const double v[3] = {x[i], y[i], z[i]};
+                for (int a = 0; a < 3; ++a) { mn[a] = fmin(mn[a], v[a]); mx[a] = fmax(mx[a], v[a]); }
             }
         }
-    } else if (ok) {
         for (int a = 0; a < 3; ++a) {
-            atomicMin(&enc[s * 6 + a], dkey(v[a]));
-            atomicMax(&enc[s * 6 + 3 + a], dkey(v[a]));
+            for (int o = 32; o > 0; o >>= 1) {
+                mn[a] = fmin(mn[a], __shfl_xor(mn[a], o));
+                mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+            }
+        }
+        if ((tid & 63) == 0) {
+            for (int a = 0; a < 3; ++a) { red[a][tid >> 6] = mn[a]; red[3 + a][tid >> 6] = mx[a]; }
+        }
+        __syncthreads();
+        if (tid < 6) {
+            double r = red[tid][0];
+            for (int w = 1; w < 4; ++w) r = tid < 3 ? fmin(r, red[tid][w]) : fmax(r, red[tid][w]);
+            if (tid < 3) atomicMin(&enc[s0 * 6 + tid], dkey(r));
+            else atomicMax(&enc[s0 * 6 + tid], dkey(r));
+        }
+    } else {
+        for (int it = 0; it < kBoxItems; ++it) {
+            const int64_t i = base + (int64_t)it * 256 + tid;
+            if (i < end) {
+                const int s = find_set(sets, nsets, i);
+                const double v[3] = {x[i], y[i], z[i]};
+                for (int a = 0; a < 3; ++a) {
+                    atomicMin(&enc[s * 6 + a], dkey(v[a]));
+                    atomicMax(&enc[s * 6 + 3 + a], dkey(v[a]));
+                }
+            }
         }
     }
 }
@@ -462,7 +487,9 @@ hipError_t launch_tree_build(Ctx *c, const sph_particles *p, hipStream_t s) {
     if (!c->prm.periodic) {
         long long *enc = reinterpret_cast<long long *>(c->d_bbox);
         k_bbox_init<<<nblk(6 * c->nsets, 256), 256, 0, s>>>(enc, c->nsets);
-        k_bbox<<<nblk(n, 256), 256, 0, s>>>(p->x, p->y, p->z, n, c->d_sets, c->nsets, enc);
+        if (n > 0)
+            k_bbox<<<nblk(n, 256 * kBoxItems), 256, 0, s>>>(p->x, p->y, p->z, n, c->d_sets,
+                                                            c->nsets, enc);
         k_bbox_finish<<<nblk(c->nsets, 64), 64, 0, s>>>(enc, c->d_sets, c->nsets);
     }
     k_sfc_keys<<<nblk(n, 256), 256, 0, s>>>(p->x, p->y, p->z, n, c->d_sets, c->nsets, c->d_key[0],
