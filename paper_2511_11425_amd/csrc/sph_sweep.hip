@@ -975,28 +975,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             auto tile = [&](auto wrap_tag) {
                 constexpr bool WRAP = decltype(wrap_tag)::value;
                 // r = 0 pairs (the particle itself, or a coincident one) count as
-                // neighbours but exert no force and no heating (x_ij = 0)
-                auto in = [&](R x, R y, R z, R h2, uint32_t &nb) -> uint32_t {
+                // neighbours but exert no force and no heating (x_ij = 0): they
+                // are accepted here and skipped in the interaction
+                auto in = [&](R x, R y, R z, R h2) -> uint32_t {
                     R dx, dy, dz;
                     const R r2 = pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
                                                          dx, dy, dz);
-                    const bool inside = r2 < Hi2 || r2 < h2;
-                    nb += inside ? 1u : 0u;
-                    return (inside && r2 > R(0)) ? 1u : 0u;
+                    return r2 < (Hi2 > h2 ? Hi2 : h2) ? 1u : 0u;
                 };
-                int interacting = 0;
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
                 tile_pairs<1>(ring, [&](int k0) {
-                    uint32_t b = 0, nb = 0;
+                    uint32_t b = 0;
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
                         const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
                                     Z = ld4(tz + k0 + h), W = ld4(th2 + k0 + h);
-                        b |= (in(X.x, Y.x, Z.x, W.x, nb) | in(X.y, Y.y, Z.y, W.y, nb) << 1 |
-                              in(X.z, Y.z, Z.z, W.z, nb) << 2 | in(X.w, Y.w, Z.w, W.w, nb) << 3)
-                             << h;
+                        b |= (in(X.x, Y.x, Z.x, W.x) | in(X.y, Y.y, Z.y, W.y) << 1 |
+                              in(X.z, Y.z, Z.z, W.z) << 2 | in(X.w, Y.w, Z.w, W.w) << 3) << h;
                     }
-                    cnt += (int)nb;
                     return b;
                 }, [&](int s, int k) {
                     return PF{s, tx[k], ty[k], tz[k], tm[k], tv[k], tq[k], sp[s], sv[s], sq[s]};
@@ -1034,7 +1030,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     const R Gbar = R(0.5) * (Gi + Gj);
                     const R mj = d.m;
                     const R sc_ = mj * (iq.x * Gi + cq.y * Gj + Pi * Gbar);
-                    if (valid) {
+                    if (valid && r2 > R(0)) {
                         atomicAdd(&acc[0][s], (double)(-sc_ * xx));
                         atomicAdd(&acc[1][s], (double)(-sc_ * xy));
                         atomicAdd(&acc[2][s], (double)(-sc_ * xz));
@@ -1042,7 +1038,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                         atomicAdd(&acc[4][s], (double)(mj * Pi * Gbar * vdotx));
                         if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
-                }, interacting);
+                }, cnt);
             };
             if (wrapf) tile(std::true_type{});
             else tile(std::false_type{});
