@@ -349,30 +349,59 @@ __device__ __forceinline__ bool point_in_ball(const double *x, const double *c, 
 // lane tests its own ball (gather) and, for the force pass, whether it lies
 // inside the bucket's box-of-balls and ball-of-balls (scatter).  Buckets that
 // no lane needs are dropped (order kept), so the tiles carry fewer candidates.
+// The bounds of kRefineBatch buckets are loaded together (one lane each) into
+// an LDS stage, so the per-bucket tests do not wait on one global load after
+// another.  The stage holds kRefineBatch x 16 doubles (structure of arrays).
+constexpr int kRefineBatch = 16;
+constexpr int kRefineStageBytes = kRefineBatch * 16 * (int)sizeof(double);
+
 template <bool SCATTER>
 __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__restrict__ nodes,
-                       const double *xi, double R, bool act, uint32_t *cand, WalkState &w) {
+                       const double *xi, double R, bool act, uint32_t *cand, double *stage,
+                       WalkState &w) {
+    const int lane = threadIdx.x;
+    constexpr int NB = kRefineBatch;
     int kept = 0;
-    for (int t = 0; t < w.ncand; ++t) {
-        const uint32_t b = __builtin_amdgcn_readfirstlane(cand[t]);
-        const Node *nd = nodes + g.node0 + g.nbp + ((int64_t)b - g.b0);
-        bool ok = false;
-        if (act) {
-            double clo[3] = {nd->clo[0], nd->clo[1], nd->clo[2]};
-            double chi[3] = {nd->chi[0], nd->chi[1], nd->chi[2]};
-            ok = ball_box(xi, R, clo, chi, g, per, slop);
-            if (SCATTER && !ok) {
-                double blo[3] = {nd->blo[0], nd->blo[1], nd->blo[2]};
-                double bhi[3] = {nd->bhi[0], nd->bhi[1], nd->bhi[2]};
-                double bc[3] = {nd->bc[0], nd->bc[1], nd->bc[2]};
-                ok = ball_box(xi, 0.0, blo, bhi, g, per, slop) &&
-                     point_in_ball(xi, bc, nd->br, g, per, slop);
+    for (int t0 = 0; t0 < w.ncand; t0 += NB) {
+        const int nb = min(NB, w.ncand - t0);
+        uint32_t bl = 0;
+        if (lane < nb) {
+            bl = cand[t0 + lane];
+            const Node *nd = nodes + g.node0 + g.nbp + ((int64_t)bl - g.b0);
+            for (int c = 0; c < 3; ++c) {
+                stage[c * NB + lane] = nd->clo[c];
+                stage[(3 + c) * NB + lane] = nd->chi[c];
+                if (SCATTER) {
+                    stage[(6 + c) * NB + lane] = nd->blo[c];
+                    stage[(9 + c) * NB + lane] = nd->bhi[c];
+                    stage[(12 + c) * NB + lane] = nd->bc[c];
+                }
+            }
+            if (SCATTER) stage[15 * NB + lane] = nd->br;
+        }
+        __syncthreads();
+        for (int u = 0; u < nb; ++u) {
+            bool ok = false;
+            if (act) {
+                const double clo[3] = {stage[u], stage[NB + u], stage[2 * NB + u]};
+                const double chi[3] = {stage[3 * NB + u], stage[4 * NB + u], stage[5 * NB + u]};
+                ok = ball_box(xi, R, clo, chi, g, per, slop);
+                if (SCATTER && !ok) {
+                    const double blo[3] = {stage[6 * NB + u], stage[7 * NB + u], stage[8 * NB + u]};
+                    const double bhi[3] = {stage[9 * NB + u], stage[10 * NB + u],
+                                           stage[11 * NB + u]};
+                    const double bc[3] = {stage[12 * NB + u], stage[13 * NB + u],
+                                          stage[14 * NB + u]};
+                    ok = ball_box(xi, 0.0, blo, bhi, g, per, slop) &&
+                         point_in_ball(xi, bc, stage[15 * NB + u], g, per, slop);
+                }
+            }
+            if (__any(ok)) {
+                if (lane == 0) cand[kept] = (uint32_t)__builtin_amdgcn_readlane((int)bl, u);
+                ++kept;
             }
         }
-        if (__any(ok)) {
-            if (threadIdx.x == 0) cand[kept] = b;
-            ++kept;
-        }
+        __syncthreads();
     }
     w.ncand = kept;
     __syncthreads();
@@ -587,7 +616,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
-    __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], tm[kWave];  // candidates
+    // candidates (x y z m); between tiles the same LDS holds the refinement stage
+    constexpr int kTileBytes = 4 * kWave * (int)sizeof(R);
+    __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
+                                                                                  : kRefineStageBytes];
+    R *const tx = reinterpret_cast<R *>(tile_buf);
+    R *const ty = tx + kWave;
+    R *const tz = ty + kWave;
+    R *const tm = tz + kWave;
+    double *const stage = reinterpret_cast<double *>(tile_buf);
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
     __shared__ double acc0[kWave], acc1[kWave], acc2[kWave];
 
@@ -659,7 +696,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                 walk_reset(stack, ws, true);
                 walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
             }
-            refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, ws);
+            refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, stage, ws);
             list_complete = (ws.nstack == 0);
             need_walk = false;
             if constexpr (MIXED) wrapf = group_needs_wrap(per, g, gext, wave_max(act ? Hw : 0.0));
@@ -692,7 +729,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     first_chunk = true;
                     continue;
                 }
-                refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, ws);
+                refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, stage, ws);
             }
             for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
                 int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
@@ -859,8 +896,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
     // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho)
-    __shared__ alignas(4 * sizeof(R)) R tx[kWave], ty[kWave], tz[kWave], th2[kWave], tm[kWave];
-    __shared__ V4<R> tv[kWave], tq[kWave];
+    // between tiles the same LDS holds the refinement stage
+    constexpr int kTileBytes = 5 * kWave * (int)sizeof(R) + 2 * kWave * (int)sizeof(V4<R>);
+    __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
+                                                                                  : kRefineStageBytes];
+    V4<R> *const tv = reinterpret_cast<V4<R> *>(tile_buf);
+    V4<R> *const tq = tv + kWave;
+    R *const tx = reinterpret_cast<R *>(tq + kWave);
+    R *const ty = tx + kWave;
+    R *const tz = ty + kWave;
+    R *const th2 = tz + kWave;
+    R *const tm = th2 + kWave;
+    double *const stage = reinterpret_cast<double *>(tile_buf);
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
     __shared__ double acc[5][kWave];
@@ -933,7 +980,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             walk_reset(stack, ws, true);
             continue;
         }
-        refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, ws);
+        refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, stage, ws);
         for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
             int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
             bool far = false;
