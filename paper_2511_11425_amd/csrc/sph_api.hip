@@ -170,6 +170,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.xs, n); A(c.ys, n); A(c.zs, n); A(c.ms, n); A(c.Hs, n);
     A(c.vxs, n); A(c.vys, n); A(c.vzs, n); A(c.us, n);
     A(c.rhos, n); A(c.oms, n); A(c.As, n); A(c.css, n); A(c.Ps, n);
+    if (c.prm.precision == SPH_PREC_MIXED) { A(c.frec1, 4 * n); A(c.frec2, 4 * n); A(c.fm, n); }
     A(c.axs, n); A(c.ays, n); A(c.azs, n); A(c.dus, n); A(c.dts, n);
     A(c.nodes, c.nnodes);
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);

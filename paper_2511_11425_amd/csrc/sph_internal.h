@@ -100,6 +100,9 @@ struct Ctx {
     double *xs = nullptr, *ys = nullptr, *zs = nullptr, *ms = nullptr, *Hs = nullptr;
     double *vxs = nullptr, *vys = nullptr, *vzs = nullptr, *us = nullptr;
     double *rhos = nullptr, *oms = nullptr, *As = nullptr, *css = nullptr, *Ps = nullptr;
+    // mixed path: FP32 force-pass records of every particle, written by the EOS
+    // pass in sorted order: (vx vy vz H), (1/H A c rho), m
+    float *frec1 = nullptr, *frec2 = nullptr, *fm = nullptr;
     double *axs = nullptr, *ays = nullptr, *azs = nullptr, *dus = nullptr, *dts = nullptr;
     // FP32 bucket-relative offsets for the mixed path
 

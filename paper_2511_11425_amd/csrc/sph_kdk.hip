@@ -51,11 +51,16 @@ __global__ void k_scatter_cols(const uint32_t *__restrict__ perm, int64_t n, Col
 
 // EOS on sorted arrays: P, c and A = P / (Omega rho^2); P and c also go to
 // the caller's arrays.
+struct ForceRecords {   // mixed path only (rec1 == nullptr otherwise)
+    const double *m, *H, *vx, *vy, *vz;
+    float *rec1, *rec2, *fm;
+};
+
 __global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, double gam, double P0,
                       const double *__restrict__ rho, const double *__restrict__ u,
                       const double *__restrict__ om, double *__restrict__ Ps,
                       double *__restrict__ cs, double *__restrict__ As,
-                      double *__restrict__ Pc, double *__restrict__ cc) {
+                      double *__restrict__ Pc, double *__restrict__ cc, ForceRecords fr) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     double r = rho[k], uu = u[k];
@@ -68,9 +73,18 @@ __global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, dou
         c2 = gam * (P + P0) / r;
     }
     double c = c2 > 0.0 ? sqrt(c2) : 0.0;
+    const double A = P / (om[k] * r * r);
     Ps[k] = P;
     cs[k] = c;
-    As[k] = P / (om[k] * r * r);
+    As[k] = A;
+    if (fr.rec1) {
+        const double H = fr.H[k];
+        float4 *r1 = reinterpret_cast<float4 *>(fr.rec1);
+        float4 *r2 = reinterpret_cast<float4 *>(fr.rec2);
+        r1[k] = make_float4((float)fr.vx[k], (float)fr.vy[k], (float)fr.vz[k], (float)H);
+        r2[k] = make_float4((float)(1.0 / H), (float)A, (float)c, (float)r);
+        fr.fm[k] = (float)fr.m[k];
+    }
     uint32_t i = perm[k];
     Pc[i] = P;
     cc[i] = c;
@@ -279,9 +293,10 @@ hipError_t launch_scatter(Ctx *c, const Cols &cols, hipStream_t s) {
 hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *c_caller,
                       hipStream_t s) {
     if (c->n == 0) return hipSuccess;
+    ForceRecords fr{c->ms, c->Hs, c->vxs, c->vys, c->vzs, c->frec1, c->frec2, c->fm};
     k_eos<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->n, c->prm.eos, c->prm.gamma,
                                                     c->prm.P0, c->rhos, u_sorted, c->oms, c->Ps,
-                                                    c->css, c->As, P_caller, c_caller);
+                                                    c->css, c->As, P_caller, c_caller, fr);
     return hipGetLastError();
 }
 

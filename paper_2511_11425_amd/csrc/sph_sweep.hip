@@ -444,6 +444,7 @@ struct SweepArgs {
     const double *xs, *ys, *zs, *ms;
     double *Hs, *rhos, *oms;
     const double *vxs, *vys, *vzs, *As, *css;
+    const float *frec1, *frec2, *fm;   // mixed force records (see the EOS pass)
     double *ax, *ay, *az, *du, *dt;
     unsigned long long *cnt;
     int B;
@@ -985,7 +986,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
             bool far = false;
             if (j >= 0) {
-                const R mj = (R)a.ms[j];
                 if constexpr (MIXED) {
                     double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
                     if (per) {
@@ -998,12 +998,20 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
                     far = needs_image(per, g, gc, gext, a.xs[j], a.ys[j], a.zs[j]);
                 }
-                tm[lane] = mj;
-                const double Hj = a.Hs[j];
-                const R Hjr = (R)Hj;
-                th2[lane] = MIXED ? Hjr * Hjr : (R)(Hj * Hj);
-                tv[lane] = V4<R>{(R)a.vxs[j], (R)a.vys[j], (R)a.vzs[j], Hjr};
-                tq[lane] = V4<R>{(R)(1.0 / Hj), (R)a.As[j], (R)a.css[j], (R)a.rhos[j]};
+                if constexpr (MIXED) {
+                    // FP32 records prepared once per particle by the EOS pass
+                    const V4<R> r1 = reinterpret_cast<const V4<R> *>(a.frec1)[j];
+                    tv[lane] = r1;
+                    tq[lane] = reinterpret_cast<const V4<R> *>(a.frec2)[j];
+                    tm[lane] = a.fm[j];
+                    th2[lane] = r1.w * r1.w;
+                } else {
+                    const double Hj = a.Hs[j];
+                    tm[lane] = (R)a.ms[j];
+                    th2[lane] = (R)(Hj * Hj);
+                    tv[lane] = V4<R>{(R)a.vxs[j], (R)a.vys[j], (R)a.vzs[j], (R)Hj};
+                    tq[lane] = V4<R>{(R)(1.0 / Hj), (R)a.As[j], (R)a.css[j], (R)a.rhos[j]};
+                }
             } else {
                 tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
                 th2[lane] = R(0);
@@ -1013,7 +1021,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
             bool wrapf = false;
             if constexpr (MIXED) {
-                double reach = fmax(Hsink_max, wave_max(j >= 0 ? a.Hs[j] : 0.0));
+                // (H of the staged candidates, 0 for empty slots; the FP32 value is
+                // within the 1e-6 margin of the test)
+                double reach = fmax(Hsink_max, wave_max((double)tv[lane].w));
                 wrapf = group_needs_wrap(per, g, gext, reach);
             } else {
                 wrapf = __any(far);
@@ -1241,6 +1251,7 @@ inline SweepArgs base_args(Ctx *c) {
     a.xs = c->xs; a.ys = c->ys; a.zs = c->zs; a.ms = c->ms;
     a.Hs = c->Hs; a.rhos = c->rhos; a.oms = c->oms;
     a.vxs = c->vxs; a.vys = c->vys; a.vzs = c->vzs; a.As = c->As; a.css = c->css;
+    a.frec1 = c->frec1; a.frec2 = c->frec2; a.fm = c->fm;
     a.cnt = c->d_cnt;
     a.B = c->bucket;
     a.periodic = c->prm.periodic;
