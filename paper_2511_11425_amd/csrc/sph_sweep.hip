@@ -232,9 +232,17 @@ struct WalkState {
     bool overflow;
 };
 
-__device__ __forceinline__ void walk_reset(uint32_t *stack, WalkState &w, bool linear) {
-    if (threadIdx.x == 0) stack[0] = 1u;
-    w.nstack = 1;
+// The walk starts from all nodes of one level of the heap (up to 64, one per
+// lane) instead of the root: a node's bounds contain its children's, so the
+// skipped ancestors could only have accepted what their descendants accept,
+// and the first, nearly empty steps of the walk are saved.
+__device__ __forceinline__ void walk_reset(uint32_t *stack, WalkState &w, bool linear,
+                                           const SetGeom &g) {
+    int d0 = g.depth < 6 ? g.depth : 6;
+    while (d0 > 0 && (2 << d0) > w.cap) --d0;
+    const int nstart = 1 << d0;
+    if ((int)threadIdx.x < nstart) stack[threadIdx.x] = (uint32_t)(nstart + (int)threadIdx.x);
+    w.nstack = nstart;
     w.ncand = 0;
     w.lin = linear ? 0 : -1;
     w.overflow = false;
@@ -689,12 +697,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     while (true) {
         if (need_walk) {
             sink_bounds(act, xi, Hw, sk);
-            walk_reset(stack, ws, linear);
+            walk_reset(stack, ws, linear, g);
             walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
             if (ws.overflow) {
                 ++overflows;
                 linear = true;
-                walk_reset(stack, ws, true);
+                walk_reset(stack, ws, true, g);
                 walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
             }
             refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, stage, ws);
@@ -718,7 +726,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     ws.ncand = 0;
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
                 } else {
-                    walk_reset(stack, ws, linear);
+                    walk_reset(stack, ws, linear, g);
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
                 }
                 if (ws.overflow) {
@@ -966,7 +974,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     double acc_d[5] = {0, 0, 0, 0, 0};
     int cnt = 0;
     unsigned long long cand_tested = 0;
-    walk_reset(stack, ws, linear);
+    walk_reset(stack, ws, linear, g);
 
     while (true) {
         walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
@@ -978,7 +986,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             cnt = 0;
             cand_tested = 0;
             amu[lane] = 0;
-            walk_reset(stack, ws, true);
+            walk_reset(stack, ws, true, g);
             continue;
         }
         refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, stage, ws);
@@ -1160,7 +1168,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
     Sink sk;
     sink_bounds(act, xi, Hd, sk);
     WalkState ws{0, 0, -1, a.stack_limit, false};
-    walk_reset(stack, ws, false);
+    walk_reset(stack, ws, false, g);
     int64_t cnt = 0;
     int overflows = 0;
     while (true) {
@@ -1168,7 +1176,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
         if (ws.overflow) {
             ++overflows;
             cnt = 0;
-            walk_reset(stack, ws, true);
+            walk_reset(stack, ws, true, g);
             continue;
         }
         for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
