@@ -617,10 +617,10 @@ __device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const do
 
 // ================================================================ density
 
-// The mixed density kernel is held to 168 VGPRs (three waves per SIMD; its LDS
-// allows more): latency hiding pays more than the few values it spills.
+// The density kernels are held to 168 VGPRs (three waves per SIMD; their LDS
+// allows more): latency hiding pays more than the few values FP64 spills.
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 2))) void k_density(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_density(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
