@@ -89,9 +89,10 @@ typedef struct {
     double h_max;      /* cap on H (also kept below half the periodic box).  Default 0.25. */
     double oversel;    /* the density pass searches with oversel*H so the iteration can
                           grow H without a new walk (Sec. 2.3.3).  Default 1.1. */
-    double nr_tol;     /* relative tolerance on the Newton step of H.  Default 1e-14
-                          (FP64) or 1e-5 (mixed; the mixed path then applies the final
-                          Newton step to H and rho, leaving O(tol^2) error) when 0. */
+    double nr_tol;     /* relative tolerance on the Newton step of H.  Default (when 0)
+                          1e-14 for FP64, 1e-5 for mixed.  A Halley step below
+                          sqrt(tol) H (FP64) or 2e-3 H (mixed) is taken without
+                          another scan, with rho and Omega Taylor-corrected. */
     int32_t nr_maxit;  /* iteration cap.  Default 64. */
     int32_t bucket;    /* particles per bucket: 8, 16, 32 or 64; 0 = autotuned.  Default 32. */
     int32_t stack_limit; /* entries of the per-wavefront walk stack in use, 2..1024 (0 = 1024).
@@ -177,8 +178,9 @@ sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int
                          int32_t *idx, int64_t capacity, int64_t *needed, void *stream);
 
 /* Density pass (Sec. 2.3.3) on the current tree: per particle, H solving
- * (4 pi/3) H^3 rho(H) = n_ngb m_i by safeguarded Newton iteration on the
- * over-selected candidate list, rho = sum_{G_i + i} m_j W(r_ij, H_i), and
+ * (4 pi/3) H^3 rho(H) = n_ngb m_i by a bracket-safeguarded Halley iteration
+ * (Newton with the second derivative of the same sums) on the over-selected
+ * candidate list, rho = sum_{G_i + i} m_j W(r_ij, H_i), and
  * Omega = 1 + (H/(3 rho)) d rho/dH.  Reads H as the first guess; writes H,
  * rho, omega; refits the ball bounds of the tree with the new H. */
 sph_status sph_density(sph_ctx *ctx, sph_particles *p, void *stream);

@@ -5,17 +5,21 @@
 //             tests of Sec. 2.3.2 / Fig. 1: gather = sink box-of-balls AND
 //             sink ball-of-balls overlap the source cell bound; scatter =
 //             source box-of-balls AND ball-of-balls overlap the sink cell
-//             bound.  64 nodes are tested per step (one per lane); accepted
-//             children are pushed and accepted buckets appended to an LDS
-//             candidate list by ballot + popcount compaction.  The list holds
-//             whole buckets; pairs are selected later (Sec. 2.3.2: lists are
-//             not pruned pairwise during the walk).
-//   density   candidate buckets are staged 64 particles at a time into LDS;
-//             each lane (one sink particle) tests r^2 < H_i^2 against the
-//             broadcast tile and accumulates the density sum and dH-derivative
-//             (eq:Density_estimate).  The Newton iteration on H (Sec. 2.3.3)
-//             re-scans the same candidate list; the walk used oversel*H so H
-//             can grow, and a group whose H outgrows it is re-walked.
+//             bound.  Up to 64 nodes are tested per step (one per lane);
+//             accepted children are pushed and accepted buckets appended to
+//             an LDS candidate list by ballot + popcount compaction.  The
+//             list holds whole buckets (Sec. 2.3.2: lists are not pruned
+//             pairwise during the walk); a per-sink refinement then drops
+//             buckets that no sink of the group needs.
+//   tiles     candidate buckets are staged 64 particles at a time into LDS;
+//             each lane (one sink) tests its distance to every staged
+//             candidate, the accepted pairs go through a small LDS ring and
+//             are evaluated one pair per lane (see "pair compaction").
+//   density   the pairs add m f, m q f' and m (2 q f' + q^2 f'') to per-sink
+//             sums (eq:Density_estimate and its H derivatives); a Halley
+//             iteration on the constant kernel mass (Sec. 2.3.3) re-scans the
+//             same candidate list (the walk used oversel*H so H can grow; a
+//             group whose H outgrows it is re-walked).
 //   forces    same structure over the gather-or-scatter list with the
 //             symmetrised pressure force, PdV du/dt, Monaghan viscosity and
 //             the time-step limits (Sec. 2.3.5, 2.3.6).
