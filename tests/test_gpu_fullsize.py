@@ -66,7 +66,7 @@ def test_fullsize_density_sampled(sph, orc, cfg, precision):
 
 
 @pytest.mark.parametrize("cfg,precision", [("large", "fp64"), ("large", "mixed"),
-                                           ("two_phase", "mixed")])
+                                           ("two_phase", "mixed"), ("two_phase", "fp64")])
 def test_fullsize_forces_sampled(sph, orc, cfg, precision):
     c = si.config_large() if cfg == "large" else si.config_two_phase()
     s, p = c["state"], c["params"]
@@ -124,3 +124,36 @@ def test_fullsize_neighbor_sets_symmetric(sph):
         g = (j * A + rowid * B) % 1000000007
         assert int(f.sum()) == int(g.sum())
     assert ctx.stats()["n_overflow"] == 0
+
+
+@pytest.fixture(scope="module")
+def spheres():
+    return si.config_spheres()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_spheres_16m_density_sampled(sph, orc, spheres, precision):
+    """The 16.8M-particle open-boundary workload (two spheres, stiffened gas):
+    smoothing lengths, densities and Omega of sampled rows against the
+    oracle's row-subset solve, in the launch configuration the benchmark
+    times."""
+    c = spheres
+    s, p = c["state"], c["params"]
+    n = len(s["x"])
+    print(f"spheres density {n} {precision}", flush=True)
+    P = sph.ParticleArrays.from_state(s)
+    ctx = sph.Context(dict(p, precision=precision))
+    ctx.build_tree(P)
+    ctx.density(P)
+    st = ctx.stats()
+    assert st["n_overflow"] == 0
+    got = P.numpy()
+    rows = rows_sample(n, k=1000, seed=7)
+    ref = orc.solve_h(p, s["x"], s["y"], s["z"], s["m"], s["H"], rows=rows)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for k in ("H", "rho"):
+        err = np.max(np.abs(got[k][rows] - ref[k]) / np.abs(ref[k]))
+        print(f"  {k} max rel err {err:.3e}", flush=True)
+        assert err < tol, k
+    err = np.max(np.abs(got["omega"][rows] - ref["omega"]) / np.abs(ref["omega"]))
+    assert err < (1e-12 if precision == "fp64" else 1e-4)
