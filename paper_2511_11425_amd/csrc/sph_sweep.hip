@@ -578,6 +578,10 @@ __device__ __forceinline__ V4<R> ld4(const R *p) { return *reinterpret_cast<cons
 // one ulp, the mixed path's tolerance is far wider), IEEE in FP64.
 __device__ __forceinline__ float pair_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double pair_sqrt(double x) { return sqrt(x); }
+// Reciprocal in the force pair terms: the hardware instruction in FP32 (about
+// one ulp), a correctly rounded division in FP64.
+__device__ __forceinline__ float pair_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double pair_rcp(double x) { return 1.0 / x; }
 
 // Pair difference d = x_k - x_i (candidate minus sink).  FP64: absolute
 // coordinates, minimum image in tiles that may need it (WRAP), distance
@@ -923,7 +927,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     double *const stage = reinterpret_cast<double *>(tile_buf);
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
-    __shared__ double acc[5][kWave];
+    __shared__ double acc[4][kWave];   // a_x a_y a_z du/dt
     __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
 
     const int lane = threadIdx.x;
@@ -965,7 +969,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     sv[lane] = V4<R>{(R)(act ? a.vxs[i] : 0.0), (R)(act ? a.vys[i] : 0.0),
                      (R)(act ? a.vzs[i] : 0.0), act ? R(1) / Hi : R(0)};
     sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), R(0)};
-    for (int q = 0; q < 5; ++q) acc[q][lane] = 0;
+    for (int q = 0; q < 4; ++q) acc[q][lane] = 0;
     amu[lane] = 0;
     const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
 
@@ -975,7 +979,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     bool linear = false;
     int overflows = 0;
 
-    double acc_d[5] = {0, 0, 0, 0, 0};
+    double acc_d[4] = {0, 0, 0, 0};
     int cnt = 0;
     unsigned long long cand_tested = 0;
     walk_reset(stack, ws, linear, g);
@@ -986,7 +990,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             // restart the whole pass with the linear bucket test
             ++overflows;
             linear = true;
-            for (int q = 0; q < 5; ++q) acc_d[q] = 0;
+            for (int q = 0; q < 4; ++q) acc_d[q] = 0;
             cnt = 0;
             cand_tested = 0;
             amu[lane] = 0;
@@ -1053,7 +1057,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     return r2 < (Hi2 > h2 ? Hi2 : h2) ? 1u : 0u;
                 };
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
-                tile_pairs<1>(ring, [&](int k0) {
+                tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0) {
                     uint32_t b = 0;
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
@@ -1089,12 +1093,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     const R wx = iv.x - cv.x, wy = iv.y - cv.y, wz = iv.z - cv.z;
                     const R vdotx = wx * xx + wy * xy + wz * xz;
                     const R hbar = R(0.25) * (Hs_ + Hj);
-                    const R mu = hbar * vdotx / (r2 + eps * hbar * hbar);
+                    const R mu = hbar * vdotx * pair_rcp(r2 + eps * hbar * hbar);
                     R Pi = 0;
                     if (vdotx < R(0)) {
                         const R cbar = R(0.5) * (iq.y + cq.z);
                         const R rbar = R(0.5) * (iq.z + cq.w);
-                        Pi = (-alpha * cbar * mu + beta * mu * mu) / rbar;
+                        Pi = (-alpha * cbar * mu + beta * mu * mu) * pair_rcp(rbar);
                     }
                     const R Gbar = R(0.5) * (Gi + Gj);
                     const R mj = d.m;
@@ -1103,8 +1107,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                         atomicAdd(&acc[0][s], (double)(-sc_ * xx));
                         atomicAdd(&acc[1][s], (double)(-sc_ * xy));
                         atomicAdd(&acc[2][s], (double)(-sc_ * xz));
-                        atomicAdd(&acc[3][s], (double)(mj * Gi * vdotx));
-                        atomicAdd(&acc[4][s], (double)(mj * Pi * Gbar * vdotx));
+                        // du/dt: A_i m_j G_i v.x + (1/2) m_j Pi Gbar v.x (A_i is the sink's)
+                        atomicAdd(&acc[3][s], (double)(mj * vdotx * (iq.x * Gi + R(0.5) * Pi * Gbar)));
                         if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
                 }, cnt);
@@ -1112,7 +1116,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             if (wrapf) tile(std::true_type{});
             else tile(std::false_type{});
             __syncthreads();
-            for (int q = 0; q < 5; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 acc_d[q] += acc[q][lane];
                 acc[q][lane] = 0;
             }
@@ -1127,7 +1131,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
         a.ax[i] = axv;
         a.ay[i] = ayv;
         a.az[i] = azv;
-        a.du[i] = (double)Ai * acc_d[3] + 0.5 * acc_d[4];
+        a.du[i] = acc_d[3];
         double amag = sqrt(axv * axv + ayv * ayv + azv * azv);
         double dtv = a.dt_max;
         if (amag > 0.0) dtv = fmin(dtv, a.eta_a * sqrt(Hd / amag));
