@@ -95,7 +95,7 @@ typedef struct {
                           another scan, with rho and Omega Taylor-corrected. */
     int32_t nr_maxit;  /* iteration cap.  Default 64. */
     int32_t bucket;    /* particles per bucket: 8, 16, 32 or 64; 0 = autotuned.  Default 32. */
-    int32_t stack_limit; /* entries of the per-wavefront walk stack in use, 2..1024 (0 = 1024).
+    int32_t stack_limit; /* entries of the per-wavefront walk stack in use, 2..768 (0 = 768).
                             A walk that would outgrow it restarts as a test of every bucket
                             of the set; results do not change, only the cost. */
     int32_t reserved;  /* must be 0 */

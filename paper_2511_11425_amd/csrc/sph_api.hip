@@ -84,7 +84,7 @@ bool valid_params(const sph_params *p, std::string &why) {
         why = "bucket must be 0, 8, 16, 32 or 64"; return false;
     }
     if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
-        why = "stack_limit must be 0 or 2..1024"; return false;
+        why = "stack_limit must be 0 or 2..768"; return false;
     }
     if (p->reserved != 0) { why = "reserved must be 0"; return false; }
     return true;

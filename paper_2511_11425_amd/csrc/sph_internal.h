@@ -15,7 +15,7 @@ namespace sphmi {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kGroup = 64;         // sink group: one wavefront, one particle per lane
-constexpr int kStackCap = 1024;    // per-wave walk stack (node ids) in LDS
+constexpr int kStackCap = 768;     // per-wave walk stack (node ids) in LDS
 constexpr int kCandCap = 256;      // per-wave candidate-bucket list in LDS
 constexpr int kMaxRow = 4096;      // longest neighbour row sph_neighbors can sort
 

@@ -494,6 +494,29 @@ __device__ __forceinline__ int64_t slot_index(const SetGeom &g, const uint32_t *
     return j < g.p1 ? j : -1;
 }
 
+// Tile composition of the mixed density and force sweeps.  The candidate slots
+// of a list (ncand buckets of B) are cut into runs of 8; tile t of the T =
+// ceil(ncand B / 64) tiles takes runs t, T + t, ..., 7T + t (lane 8c + e holds
+// slot 8(cT + t) + e).  Each tile thus samples the whole neighbourhood of the
+// group instead of 64/B adjacent buckets, so the sinks' hit counts per tile are
+// even and the compaction, whose rounds number the largest count of any sink,
+// needs about half as many rounds.  The FP64 sweeps keep adjacent buckets
+// (slot_index): there a tile takes the minimum-image path as soon as one of
+// its candidates may need it, which interleaved tiles of a group near the box
+// edge nearly all would.  Returns the sorted particle index or -1.
+__device__ __forceinline__ int sweep_tiles(int ncand, int B) {
+    return (ncand * B + kWave - 1) / kWave;
+}
+__device__ __forceinline__ int64_t sweep_slot(const SetGeom &g, const uint32_t *cand, int ncand,
+                                              int t, int T, int lb) {
+    const int lane = threadIdx.x;
+    const int p = 8 * ((lane >> 3) * T + t) + (lane & 7);
+    const int bi = p >> lb;
+    if (bi >= ncand) return -1;
+    const int64_t j = g.p0 + ((int64_t)cand[bi] - g.b0) * ((int64_t)1 << lb) + (p & ((1 << lb) - 1));
+    return j < g.p1 ? j : -1;
+}
+
 // Four values staged together so one LDS instruction moves them.
 template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 
@@ -650,6 +673,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
+    const int lb = 31 - __builtin_clz((unsigned)a.B);   // B = 2^lb
     const double slop = set_slop(g);
     const double cap = set_hcap(g, per, a.h_max);
     const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
@@ -748,8 +772,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                 }
                 refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, stage, ws);
             }
-            for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
-                int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+            const int ntile = sweep_tiles(ws.ncand, a.B);
+            for (int t = 0; t < ntile; ++t) {
+                int64_t j = MIXED ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
+                                  : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
                 bool far = false;
                 if (j >= 0) {
                     const R mj = (R)a.ms[j];
@@ -935,6 +961,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
+    const int lb = 31 - __builtin_clz((unsigned)a.B);   // B = 2^lb
     const double slop = set_slop(g);
     const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
     const bool act = i < g.p1;
@@ -998,8 +1025,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             continue;
         }
         refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, stage, ws);
-        for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
-            int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+        const int ntile = sweep_tiles(ws.ncand, a.B);
+        for (int t = 0; t < ntile; ++t) {
+            int64_t j = MIXED ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
+                              : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
             bool far = false;
             if (j >= 0) {
                 if constexpr (MIXED) {
