@@ -234,6 +234,7 @@ struct WalkState {
     int lin;
     int cap;       // stack entries in use (<= kStackCap)
     bool overflow;
+    bool far;      // after refine: a kept bucket may need the periodic image
 };
 
 // The walk starts from all nodes of one level of the heap (up to 64, one per
@@ -364,25 +365,34 @@ __device__ __forceinline__ bool point_in_ball(const double *x, const double *c, 
 // The bounds of kRefineBatch buckets are loaded together (one lane each) into
 // an LDS stage, so the per-bucket tests do not wait on one global load after
 // another.  The stage holds kRefineBatch x 16 doubles (structure of arrays).
+// `w.far` reports whether any kept bucket reaches within the group's extent
+// gext of half a box from the group centre gc on some axis, i.e. whether one of
+// its particles may need the minimum image (a superset of `needs_image`, as
+// every particle lies inside its bucket's cell bound).
 constexpr int kRefineBatch = 16;
 constexpr int kRefineStageBytes = kRefineBatch * 16 * (int)sizeof(double);
 
 template <bool SCATTER>
 __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__restrict__ nodes,
-                       const double *xi, double R, bool act, uint32_t *cand, double *stage,
-                       WalkState &w) {
+                       const double *xi, double R, bool act, const double *gc,
+                       const double *gext, uint32_t *cand, double *stage, WalkState &w) {
     const int lane = threadIdx.x;
     constexpr int NB = kRefineBatch;
     int kept = 0;
+    bool far = false;
     for (int t0 = 0; t0 < w.ncand; t0 += NB) {
         const int nb = min(NB, w.ncand - t0);
         uint32_t bl = 0;
+        int bfar = 0;
         if (lane < nb) {
             bl = cand[t0 + lane];
             const Node *nd = nodes + g.node0 + g.nbp + ((int64_t)bl - g.b0);
             for (int c = 0; c < 3; ++c) {
-                stage[c * NB + lane] = nd->clo[c];
-                stage[(3 + c) * NB + lane] = nd->chi[c];
+                const double lo = nd->clo[c], hi = nd->chi[c];
+                stage[c * NB + lane] = lo;
+                stage[(3 + c) * NB + lane] = hi;
+                if (per && fmax(fabs(lo - gc[c]), fabs(hi - gc[c])) + gext[c] >= 0.999 * g.halfL[c])
+                    bfar = 1;
                 if (SCATTER) {
                     stage[(6 + c) * NB + lane] = nd->blo[c];
                     stage[(9 + c) * NB + lane] = nd->bhi[c];
@@ -410,12 +420,14 @@ __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__re
             }
             if (__any(ok)) {
                 if (lane == 0) cand[kept] = (uint32_t)__builtin_amdgcn_readlane((int)bl, u);
+                far = far || __builtin_amdgcn_readlane(bfar, u) != 0;
                 ++kept;
             }
         }
         __syncthreads();
     }
     w.ncand = kept;
+    w.far = far;
     __syncthreads();
 }
 
@@ -494,23 +506,26 @@ __device__ __forceinline__ int64_t slot_index(const SetGeom &g, const uint32_t *
     return j < g.p1 ? j : -1;
 }
 
-// Tile composition of the mixed density and force sweeps.  The candidate slots
-// of a list (ncand buckets of B) are cut into runs of 8; tile t of the T =
-// ceil(ncand B / 64) tiles takes runs t, T + t, ..., 7T + t (lane 8c + e holds
-// slot 8(cT + t) + e).  Each tile thus samples the whole neighbourhood of the
-// group instead of 64/B adjacent buckets, so the sinks' hit counts per tile are
-// even and the compaction, whose rounds number the largest count of any sink,
-// needs about half as many rounds.  The FP64 sweeps keep adjacent buckets
-// (slot_index): there a tile takes the minimum-image path as soon as one of
-// its candidates may need it, which interleaved tiles of a group near the box
-// edge nearly all would.  Returns the sorted particle index or -1.
+// Tile composition of the density and force sweeps.  The candidate slots of a
+// list (ncand buckets of B) are cut into runs of kRun; tile t of the T =
+// ceil(ncand B / 64) tiles takes runs t, T + t, 2T + t, ... (lane kRun c + e
+// holds slot kRun (cT + t) + e).  Each tile thus samples the whole
+// neighbourhood of the group instead of 64/B adjacent buckets, so the sinks'
+// hit counts per tile are even and the compaction, whose rounds number the
+// largest count of any sink, needs about half as many rounds.  (Runs of 2
+// measured as fast as single slots and faster than runs of 4 or 8.)  An FP64
+// tile takes the minimum-image path as soon as one of its candidates may need
+// it, which interleaved tiles of a group near the box edge nearly all would;
+// such lists (refine's `far`) keep adjacent buckets per tile (slot_index).
+// Returns the sorted particle index or -1.
 __device__ __forceinline__ int sweep_tiles(int ncand, int B) {
     return (ncand * B + kWave - 1) / kWave;
 }
 __device__ __forceinline__ int64_t sweep_slot(const SetGeom &g, const uint32_t *cand, int ncand,
                                               int t, int T, int lb) {
+    constexpr int kRun = 2;
     const int lane = threadIdx.x;
-    const int p = 8 * ((lane >> 3) * T + t) + (lane & 7);
+    const int p = kRun * ((lane / kRun) * T + t) + (lane % kRun);
     const int bi = p >> lb;
     if (bi >= ncand) return -1;
     const int64_t j = g.p0 + ((int64_t)cand[bi] - g.b0) * ((int64_t)1 << lb) + (p & ((1 << lb) - 1));
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     acc0[lane] = 0; acc1[lane] = 0; acc2[lane] = 0;
     bool wrapf = false;
 
-    WalkState ws{0, 0, -1, a.stack_limit, false};
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
     Sink sk;
     bool list_complete = false;
     bool linear = false;
@@ -737,7 +752,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                 walk_reset(stack, ws, true, g);
                 walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
             }
-            refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, stage, ws);
+            refine<false>(g, per, slop, a.nodes, xi, Hw, act, gc, gext, cand, stage, ws);
             list_complete = (ws.nstack == 0);
             need_walk = false;
             if constexpr (MIXED) wrapf = group_needs_wrap(per, g, gext, wave_max(act ? Hw : 0.0));
@@ -770,12 +785,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                     first_chunk = true;
                     continue;
                 }
-                refine<false>(g, per, slop, a.nodes, xi, Hw, act, cand, stage, ws);
+                refine<false>(g, per, slop, a.nodes, xi, Hw, act, gc, gext, cand, stage, ws);
             }
             const int ntile = sweep_tiles(ws.ncand, a.B);
             for (int t = 0; t < ntile; ++t) {
-                int64_t j = MIXED ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
-                                  : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+                int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
+                                               : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
                 bool far = false;
                 if (j >= 0) {
                     const R mj = (R)a.ms[j];
@@ -1002,7 +1017,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
 
     Sink sk;
     sink_bounds(act, xi, Hd, sk);
-    WalkState ws{0, 0, -1, a.stack_limit, false};
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
     bool linear = false;
     int overflows = 0;
 
@@ -1024,11 +1039,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
             walk_reset(stack, ws, true, g);
             continue;
         }
-        refine<true>(g, per, slop, a.nodes, xi, Hd, act, cand, stage, ws);
+        refine<true>(g, per, slop, a.nodes, xi, Hd, act, gc, gext, cand, stage, ws);
         const int ntile = sweep_tiles(ws.ncand, a.B);
         for (int t = 0; t < ntile; ++t) {
-            int64_t j = MIXED ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
-                              : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+            int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
+                                           : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
             bool far = false;
             if (j >= 0) {
                 if constexpr (MIXED) {
@@ -1204,7 +1219,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
 
     Sink sk;
     sink_bounds(act, xi, Hd, sk);
-    WalkState ws{0, 0, -1, a.stack_limit, false};
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
     walk_reset(stack, ws, false, g);
     int64_t cnt = 0;
     int overflows = 0;
