@@ -561,17 +561,36 @@ template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 // workgroup barrier would also wait for every outstanding LDS atomic).
 constexpr int kRing = 256;
 
-// `hit8(k0)` returns the accepted bits of candidates k0..k0+7 of this lane;
-// `fetch(s, k)` loads the operands of pair (sink s, candidate k) and
-// `apply(d, valid)` adds its contributions when `valid`.
+// Hit bits are collected most significant first: `push_hit(acc, a, b)` is
+// 2 acc + (a < b), one compare whose lane mask is the carry-in of one add, in
+// place of a compare, a select and a merge per candidate.  (The carry-out
+// overwrites the mask; nothing else reads it.)
+__device__ __forceinline__ uint32_t push_hit(uint32_t acc, float a, float b) {
+    asm("v_cmp_lt_f32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+        : "+v"(acc) : "v"(a), "v"(b) : "vcc");
+    return acc;
+}
+__device__ __forceinline__ uint32_t push_hit(uint32_t acc, double a, double b) {
+    asm("v_cmp_lt_f64 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+        : "+v"(acc) : "v"(a), "v"(b) : "vcc");
+    return acc;
+}
+
+// `hit8(k0, acc)` pushes the hits of candidates k0..k0+7 of this lane, in
+// that order, onto acc (push_hit); candidate c of the tile ends at bit 63 - c
+// of the lane's mask.  `fetch(s, k)` loads the operands of pair (sink s,
+// candidate k) and `apply(d, valid)` adds its contributions when `valid`.
 template <int U, class Hit8, class Fetch, class Apply>
 __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetch, Apply apply,
                                            int &hits) {
     static_assert(U * kWave + kWave <= kRing, "pair ring too small");
     const int lane = threadIdx.x;
-    uint64_t m = 0;
+    uint32_t first = 0, second = 0;   // candidates 0..31, 32..63
 #pragma unroll 1
-    for (int k0 = 0; k0 < kWave; k0 += 8) m |= (uint64_t)hit8(k0) << k0;
+    for (int k0 = 0; k0 < kWave / 2; k0 += 8) first = hit8(k0, first);
+#pragma unroll 1
+    for (int k0 = kWave / 2; k0 < kWave; k0 += 8) second = hit8(k0, second);
+    uint64_t m = ((uint64_t)first << 32) | second;
     hits += __popcll(m);
     int produced = 0, consumed = 0;
     auto run = [&](int n) {   // pairs consumed .. consumed + n - 1, n <= U * 64
@@ -591,12 +610,11 @@ __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetc
         const bool h = m != 0ull;
         const uint64_t bal = __ballot(h);
         if (bal == 0ull) break;
-        if (h) {
-            const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            ring[(produced + below) & (kRing - 1)] = (uint16_t)((lane << 6) | __builtin_ctzll(m));
-            m &= m - 1ull;
-        }
+        // ring slot: `produced` plus the entries of lower lanes in this round
+        const uint32_t slot = __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, (uint32_t)produced));
+        if (h) ring[slot & (kRing - 1)] = (uint16_t)(((lane << 6) | 63) - __builtin_ctzll(m));
+        m &= m - 1ull;   // (0 stays 0)
         produced += __popcll(bal);
         if (produced - consumed >= U * kWave) {
             __builtin_amdgcn_wave_barrier();
@@ -814,20 +832,21 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                 __syncthreads();
                 auto tile = [&](auto wrap_tag) {
                     constexpr bool WRAP = decltype(wrap_tag)::value;
-                    auto in = [&](R x, R y, R z) -> uint32_t {
+                    auto r2of = [&](R x, R y, R z) -> R {
                         R dx, dy, dz;
                         return pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
-                                                       dx, dy, dz) < H2 ? 1u : 0u;
+                                                       dx, dy, dz);
                     };
                     struct PD { int s; R x, y, z, m; V4<R> si; };
-                    tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0) {
-                        uint32_t b = 0;
+                    tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0, uint32_t b) {
 #pragma unroll
                         for (int h = 0; h < 8; h += 4) {
                             const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
                                         Z = ld4(tz + k0 + h);
-                            b |= (in(X.x, Y.x, Z.x) | in(X.y, Y.y, Z.y) << 1 |
-                                  in(X.z, Y.z, Z.z) << 2 | in(X.w, Y.w, Z.w) << 3) << h;
+                            b = push_hit(b, r2of(X.x, Y.x, Z.x), H2);
+                            b = push_hit(b, r2of(X.y, Y.y, Z.y), H2);
+                            b = push_hit(b, r2of(X.z, Y.z, Z.z), H2);
+                            b = push_hit(b, r2of(X.w, Y.w, Z.w), H2);
                         }
                         return b;
                     }, [&](int s, int k) {
@@ -1094,21 +1113,22 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                 // r = 0 pairs (the particle itself, or a coincident one) count as
                 // neighbours but exert no force and no heating (x_ij = 0): they
                 // are accepted here and skipped in the interaction
-                auto in = [&](R x, R y, R z, R h2) -> uint32_t {
+                auto in = [&](uint32_t b, R x, R y, R z, R h2) -> uint32_t {
                     R dx, dy, dz;
                     const R r2 = pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
                                                          dx, dy, dz);
-                    return r2 < (Hi2 > h2 ? Hi2 : h2) ? 1u : 0u;
+                    return push_hit(b, r2, Hi2 > h2 ? Hi2 : h2);
                 };
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
-                tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0) {
-                    uint32_t b = 0;
+                tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0, uint32_t b) {
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
                         const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
                                     Z = ld4(tz + k0 + h), W = ld4(th2 + k0 + h);
-                        b |= (in(X.x, Y.x, Z.x, W.x) | in(X.y, Y.y, Z.y, W.y) << 1 |
-                              in(X.z, Y.z, Z.z, W.z) << 2 | in(X.w, Y.w, Z.w, W.w) << 3) << h;
+                        b = in(b, X.x, Y.x, Z.x, W.x);
+                        b = in(b, X.y, Y.y, Z.y, W.y);
+                        b = in(b, X.z, Y.z, Z.z, W.z);
+                        b = in(b, X.w, Y.w, Z.w, W.w);
                     }
                     return b;
                 }, [&](int s, int k) {
