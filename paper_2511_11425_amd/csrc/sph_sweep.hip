@@ -985,7 +985,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     R *const th2 = tz + kWave;
     R *const tm = th2 + kWave;
     double *const stage = reinterpret_cast<double *>(tile_buf);
-    __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink:      (x H) (v 1/H) (A c rho -)
+    __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink: (x H) (v 1/H) (A c rho sigma/H^5)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
     __shared__ double acc[4][kWave];   // a_x a_y a_z du/dt
     __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
@@ -1029,7 +1029,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
     sp[lane] = V4<R>{qx, qy, qz, Hi};
     sv[lane] = V4<R>{(R)(act ? a.vxs[i] : 0.0), (R)(act ? a.vys[i] : 0.0),
                      (R)(act ? a.vzs[i] : 0.0), act ? R(1) / Hi : R(0)};
-    sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), R(0)};
+    const double hinv_i = act ? 1.0 / Hd : 0.0, h2_i = hinv_i * hinv_i;
+    sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), (R)(sigma_of<K>() * h2_i * h2_i * hinv_i)};
     for (int q = 0; q < 4; ++q) acc[q][lane] = 0;
     amu[lane] = 0;
     const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
@@ -1142,11 +1143,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
                     const R r = pair_sqrt(r2);
                     const R Hs_ = ip.w, Hj = cv.w;
                     R Gi = 0, Gj = 0;
-                    if (r2 < Hs_ * Hs_) {
-                        const R hinv = iv.w;
-                        const R h2 = hinv * hinv;
-                        Gi = sig * shape_g<K, R>(r * hinv, Hs_, r) * (h2 * h2 * hinv);
-                    }
+                    if (r2 < Hs_ * Hs_)   // the sink's sigma / H^5 is prepared once
+                        Gi = iq.w * shape_g<K, R>(r * iv.w, Hs_, r);
                     if (r2 < Hj * Hj) {
                         const R hinv = cq.x;
                         const R h2 = hinv * hinv;
