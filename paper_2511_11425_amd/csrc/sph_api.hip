@@ -174,6 +174,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.axs, n); A(c.ays, n); A(c.azs, n); A(c.dus, n); A(c.dts, n);
     A(c.nodes, c.nnodes);
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
+    A(c.hprev, n);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
     A(c.d_rep, 1);
@@ -473,6 +474,8 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     st = sph_build_tree(ctx, p, n, stream);
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s), "counters");
+    HIPCHK(ctx, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.hprev), c.n, 0ull, s),
+           "H history");
     st = do_density(ctx, p, s);
     if (st != SPH_OK) return st;
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, false, s);

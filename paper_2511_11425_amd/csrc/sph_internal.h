@@ -110,6 +110,7 @@ struct Ctx {
 
     // predictor scratch (caller order) for the step
     double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *upred = nullptr;
+    double *hprev = nullptr;   // caller order: converged H of the step before (0 = none)
 
     // scan scratch
     int64_t *d_scan_tmp = nullptr;

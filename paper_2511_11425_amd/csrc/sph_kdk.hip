@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kThreads) void k_set_min_dt(const double *__restric
 //   x     += dt v_half, wrapped into the periodic box
 struct KickArgs {
     double *x, *y, *z, *vx, *vy, *vz, *u;
+    double *H, *Hprev;
     const double *ax, *ay, *az, *du;
     double *vpx, *vpy, *vpz, *up;
     const SetGeom *sets;
@@ -194,6 +195,13 @@ __global__ void k_kick_drift(KickArgs a) {
         nz = wrap_box(nz, g.lo[2], g.L[2]);
     }
     a.x[i] = nx; a.y[i] = ny; a.z[i] = nz;
+    // First guess of the density pass's smoothing-length iteration: the
+    // converged H extrapolated by its change over the last step (ratio held
+    // to [0.95, 1.05]).  The iteration converges to the same root from any
+    // guess; a closer guess saves a scan of the candidates (Sec. 2.3.3).
+    const double Hn = a.H[i], Hp = a.Hprev[i];
+    a.Hprev[i] = Hn;
+    if (Hp > 0.0 && Hn > 0.0) a.H[i] = Hn * fmin(fmax(Hn / Hp, 0.95), 1.05);
 }
 
 // Closing kick: v = v_half + (dt/2) a_new, u likewise.
@@ -318,6 +326,7 @@ hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s) {
     if (c->n == 0) return hipSuccess;
     KickArgs a;
     a.x = p->x; a.y = p->y; a.z = p->z; a.vx = p->vx; a.vy = p->vy; a.vz = p->vz; a.u = p->u;
+    a.H = p->H; a.Hprev = c->hprev;
     a.ax = p->ax; a.ay = p->ay; a.az = p->az; a.du = p->dudt;
     a.vpx = c->vpx; a.vpy = c->vpy; a.vpz = c->vpz; a.up = c->upred;
     a.sets = c->d_sets; a.nsets = c->nsets; a.periodic = c->prm.periodic;
