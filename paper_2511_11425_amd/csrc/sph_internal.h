@@ -60,7 +60,7 @@ struct SetGeom {
 // One tree node: cell bound (AABB of positions), box-of-balls (AABB of the
 // kernel balls) and ball-of-balls (an enclosing sphere of the kernel balls),
 // Sec. 2.3.2 and Fig. 1.  Empty nodes have clo > chi.
-struct Node {
+struct alignas(16) Node {
     double clo[3], chi[3];
     double blo[3], bhi[3];
     double bc[3], br;

@@ -297,17 +297,15 @@ __device__ void walk(const SetGeom &g, bool per, double slop, const Node *__rest
         __syncthreads();
         bool ok = false;
         if (lane < k) {
-            const Node *nd = nodes + g.node0 + h;
-            double clo[3] = {nd->clo[0], nd->clo[1], nd->clo[2]};
-            double chi[3] = {nd->chi[0], nd->chi[1], nd->chi[2]};
-            ok = box_box(sk.blo, sk.bhi, clo, chi, g, per, slop) &&
-                 ball_box(sk.bc, sk.br, clo, chi, g, per, slop);
-            if (SCATTER && !ok) {
-                double blo[3] = {nd->blo[0], nd->blo[1], nd->blo[2]};
-                double bhi[3] = {nd->bhi[0], nd->bhi[1], nd->bhi[2]};
-                double bc[3] = {nd->bc[0], nd->bc[1], nd->bc[2]};
-                ok = box_box(blo, bhi, sk.clo, sk.chi, g, per, slop) &&
-                     ball_box(bc, nd->br, sk.clo, sk.chi, g, per, slop);
+            // all bounds of the node are read at once: each step of the walk
+            // then waits for one round trip to memory, not two
+            const Node nd = nodes[g.node0 + h];
+            ok = box_box(sk.blo, sk.bhi, nd.clo, nd.chi, g, per, slop) &&
+                 ball_box(sk.bc, sk.br, nd.clo, nd.chi, g, per, slop);
+            if (SCATTER) {
+                const bool sc = box_box(nd.blo, nd.bhi, sk.clo, sk.chi, g, per, slop) &&
+                                ball_box(nd.bc, nd.br, sk.clo, sk.chi, g, per, slop);
+                ok = ok || sc;
             }
         }
         const bool leaf = h >= (uint32_t)g.nbp;
