@@ -421,11 +421,11 @@ __device__ inline void ball_union(const double *c1, double r1, const double *c2,
     *r = R * (1.0 + 1e-12) + 1e-12 * (fabs(c[0]) + fabs(c[1]) + fabs(c[2]));
 }
 
-__global__ void k_combine(const SetGeom *__restrict__ sets, int nsets,
-                          const int64_t *__restrict__ pref, int64_t total, int d,
-                          Node *__restrict__ nodes) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
+// Node t of height d (t counts the nodes of that height over all sets, in set
+// order) from its two children.
+__device__ __forceinline__ void combine_one(const SetGeom *__restrict__ sets, int nsets,
+                                            const int64_t *__restrict__ pref, int64_t t, int d,
+                                            Node *__restrict__ nodes) {
     int lo = 0, hi = nsets - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -442,6 +442,30 @@ __global__ void k_combine(const SetGeom *__restrict__ sets, int nsets,
     }
     ball_union(a.bc, a.br, b.bc, b.br, o.bc, &o.br);
     nodes[g.node0 + h] = o;
+}
+
+__global__ void k_combine(const SetGeom *__restrict__ sets, int nsets,
+                          const int64_t *__restrict__ pref, int64_t total, int d,
+                          Node *__restrict__ nodes) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < total) combine_one(sets, nsets, pref, t, d, nodes);
+}
+
+// The small top heights d0..d1 in one workgroup, height after height (each
+// height reads what the one below wrote; the barrier orders them), instead of
+// one launch per height.
+constexpr int kTopThreads = 1024;
+__global__ __launch_bounds__(kTopThreads) void k_combine_top(const SetGeom *__restrict__ sets,
+                                                             int nsets,
+                                                             const int64_t *__restrict__ pref_all,
+                                                             int d0, int d1, Node *__restrict__ nodes) {
+    for (int d = d0; d <= d1; ++d) {
+        const int64_t *pref = pref_all + (int64_t)d * (nsets + 1);
+        const int64_t total = pref[nsets];
+        for (int64_t t = threadIdx.x; t < total; t += kTopThreads)
+            combine_one(sets, nsets, pref, t, d, nodes);
+        __syncthreads();
+    }
 }
 
 inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -471,13 +495,14 @@ hipError_t launch_refit(Ctx *c, hipStream_t s) {
     if (c->nbuckets == 0) return hipSuccess;
     k_leaf_bounds<<<nblk(c->nbuckets * c->bucket, 256), 256, 0, s>>>(
         c->d_sets, c->d_bkt_set, c->nbuckets, c->bucket, c->xs, c->ys, c->zs, c->Hs, c->nodes);
-    for (int d = 1; d <= c->max_depth; ++d) {
-        int64_t tot = c->level_total[d];
-        if (tot <= 0) continue;
-        k_combine<<<nblk(tot, 128), 128, 0, s>>>(c->d_sets, c->nsets,
-                                                 c->d_level_pref + (int64_t)d * (c->nsets + 1),
-                                                 tot, d, c->nodes);
-    }
+    int d = 1;
+    for (; d <= c->max_depth && c->level_total[d] > kTopThreads; ++d)
+        k_combine<<<nblk(c->level_total[d], 128), 128, 0, s>>>(
+            c->d_sets, c->nsets, c->d_level_pref + (int64_t)d * (c->nsets + 1), c->level_total[d],
+            d, c->nodes);
+    if (d <= c->max_depth)
+        k_combine_top<<<1, kTopThreads, 0, s>>>(c->d_sets, c->nsets, c->d_level_pref, d,
+                                                c->max_depth, c->nodes);
     return hipGetLastError();
 }
 
