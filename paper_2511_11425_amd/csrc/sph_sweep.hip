@@ -679,10 +679,13 @@ __device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const do
 
 // ================================================================ density
 
-// The density kernels are held to 168 VGPRs (three waves per SIMD; their LDS
-// allows more): latency hiding pays more than the few values FP64 spills.
+// Occupancy of the density kernels (their 9-10 KiB of LDS admit up to 16
+// waves per CU): both are held to 128 VGPRs, four waves per SIMD; the values
+// that then spill to scratch cost less than the latency the extra wave hides
+// (measured at 2M from three to four waves: mixed 2.48 -> 2.21 ms, FP64
+// 7.29 -> 6.91 ms).
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_density(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_density(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
