@@ -175,6 +175,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.nodes, c.nnodes);
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
     A(c.hprev, n);
+    A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
     A(c.d_rep, 1);

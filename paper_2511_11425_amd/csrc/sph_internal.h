@@ -15,7 +15,7 @@ namespace sphmi {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kGroup = 64;         // sink group: one wavefront, one particle per lane
-constexpr int kStackCap = 768;     // per-wave walk stack (node ids) in LDS
+constexpr int kStackCap = 768;     // walk stack (node ids) of one wave
 constexpr int kCandCap = 256;      // per-wave candidate-bucket list in LDS
 constexpr int kMaxRow = 4096;      // longest neighbour row sph_neighbors can sort
 
@@ -111,6 +111,7 @@ struct Ctx {
     // predictor scratch (caller order) for the step
     double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *upred = nullptr;
     double *hprev = nullptr;   // caller order: converged H of the step before (0 = none)
+    uint32_t *d_wstack = nullptr;   // force-walk stacks, kStackCap node ids per sink group
 
     // scan scratch
     int64_t *d_scan_tmp = nullptr;

@@ -223,7 +223,8 @@ __device__ __forceinline__ bool ball_box(const double *c, double R, const double
     return d2 <= Rs * Rs;
 }
 
-// Walk state lives in LDS (stack, candidate list) and in wave-uniform registers.
+// Walk state lives in the stack (LDS, or global memory for the force kernels),
+// the LDS candidate list and wave-uniform registers.
 // In tree mode `lin` is -1; a group whose stack would overflow restarts in
 // linear mode, where `lin` is the next bucket of the set to test (every bucket
 // is tested once with the same bound tests, so the result does not depend on
@@ -479,6 +480,7 @@ struct SweepArgs {
     int64_t *row_count;     // caller order (count pass)
     const int64_t *offsets; // caller order (fill pass)
     int32_t *idx;
+    uint32_t *wstack;       // force-walk stacks (kStackCap per sink group)
 };
 
 __device__ __forceinline__ double set_slop(const SetGeom &g) {
@@ -964,13 +966,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
 
 // ================================================================ forces
 
-// The mixed force kernel is held to three waves per SIMD as well; it spills a
-// few long-lived values to scratch, which costs less than the lost latency
-// hiding at two waves.
+// Occupancy of the force kernels.  Their walk stack lives in global memory
+// (one per sink group, in L2 while the group runs), not in LDS: the 3 KiB it
+// frees bring the mixed kernel's LDS to 10 KiB, which admits four waves per
+// SIMD, and the mixed kernel is held to 128 VGPRs for them (the values that
+// spill to scratch cost less than the latency the fourth wave hides:
+// measured 4.21 -> 3.60 ms at 2M); the FP64 kernel's 16.5 KiB admit nine
+// waves per CU.
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3 : 2))) void k_forces(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 2))) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
-    __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
     // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho)
@@ -993,6 +998,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 3
 
     const int lane = threadIdx.x;
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
@@ -1331,6 +1337,7 @@ inline SweepArgs base_args(Ctx *c) {
     a.Hs = c->Hs; a.rhos = c->rhos; a.oms = c->oms;
     a.vxs = c->vxs; a.vys = c->vys; a.vzs = c->vzs; a.As = c->As; a.css = c->css;
     a.frec1 = c->frec1; a.frec2 = c->frec2; a.fm = c->fm;
+    a.wstack = c->d_wstack;
     a.cnt = c->d_cnt;
     a.B = c->bucket;
     a.periodic = c->prm.periodic;
