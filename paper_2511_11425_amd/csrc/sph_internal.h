@@ -111,7 +111,7 @@ struct Ctx {
     // predictor scratch (caller order) for the step
     double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *upred = nullptr;
     double *hprev = nullptr;   // caller order: converged H of the step before (0 = none)
-    uint32_t *d_wstack = nullptr;   // force-walk stacks, kStackCap node ids per sink group
+    uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 
     // scan scratch
     int64_t *d_scan_tmp = nullptr;

@@ -223,8 +223,9 @@ __device__ __forceinline__ bool ball_box(const double *c, double R, const double
     return d2 <= Rs * Rs;
 }
 
-// Walk state lives in the stack (LDS, or global memory for the force kernels),
-// the LDS candidate list and wave-uniform registers.
+// Walk state lives in the stack (global memory for the density and force
+// kernels, LDS for the neighbour lists), the LDS candidate list and
+// wave-uniform registers.
 // In tree mode `lin` is -1; a group whose stack would overflow restarts in
 // linear mode, where `lin` is the next bucket of the set to test (every bucket
 // is tested once with the same bound tests, so the result does not depend on
@@ -480,7 +481,7 @@ struct SweepArgs {
     int64_t *row_count;     // caller order (count pass)
     const int64_t *offsets; // caller order (fill pass)
     int32_t *idx;
-    uint32_t *wstack;       // force-walk stacks (kStackCap per sink group)
+    uint32_t *wstack;       // walk stacks of the sweeps (kStackCap per sink group)
 };
 
 __device__ __forceinline__ double set_slop(const SetGeom &g) {
@@ -681,15 +682,15 @@ __device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const do
 
 // ================================================================ density
 
-// Occupancy of the density kernels (their 9-10 KiB of LDS admit up to 16
-// waves per CU): both are held to 128 VGPRs, four waves per SIMD; the values
-// that then spill to scratch cost less than the latency the extra wave hides
-// (measured at 2M from three to four waves: mixed 2.48 -> 2.21 ms, FP64
-// 7.29 -> 6.91 ms).
+// Occupancy of the density kernels.  The walk stack lives in global memory
+// (one per sink group, as for the force kernels), leaving 6-7 KiB of LDS; the
+// mixed kernel is held to 96 VGPRs, five waves per SIMD, the FP64 one to 128,
+// four waves.  The values that then spill to scratch cost less than the
+// latency the extra waves hide (measured at 2M: mixed 2.48 ms at three
+// waves, 2.21 at four, 2.13 at five; FP64 7.29 at three, 6.83 at four).
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_density(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4))) void k_density(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
-    __shared__ uint32_t stack[kStackCap];
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
     // candidates (x y z m); between tiles the same LDS holds the refinement stage
@@ -706,6 +707,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
 
     const int lane = threadIdx.x;
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
