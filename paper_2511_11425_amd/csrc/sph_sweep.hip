@@ -357,27 +357,50 @@ __device__ __forceinline__ bool point_in_ball(const double *x, const double *c, 
     return d2 <= Rs * Rs;
 }
 
+// Four values staged together so one LDS instruction moves them.
+template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
+
+// Four consecutive entries of an LDS array (one 128-bit read for FP32).
+template <typename R>
+__device__ __forceinline__ V4<R> ld4(const R *p) { return *reinterpret_cast<const V4<R> *>(p); }
+
 // Per-sink refinement of the candidate buckets: the group-level bounds of the
 // walk accept a bucket when it may hold a neighbour of ANY sink; here every
 // lane tests its own ball (gather) and, for the force pass, whether it lies
 // inside the bucket's box-of-balls and ball-of-balls (scatter).  Buckets that
 // no lane needs are dropped (order kept), so the tiles carry fewer candidates.
-// The bounds of kRefineBatch buckets are loaded together (one lane each) into
-// an LDS stage, so the per-bucket tests do not wait on one global load after
-// another.  The stage holds kRefineBatch x 16 doubles (structure of arrays).
+// Dropping a bucket is the only decision made here: keeping one too many costs
+// time, never results.
+//
+// The tests run branch-free in FP32 on bounds relative to the group centre
+// gc.  The lane that loads a bucket (kRefineBatch at a time, one per lane)
+// turns each bound into a centre offset from gc (its minimum image when
+// periodic) and a half width or radius, widened by 1e-5 of the bound's reach
+// plus the set's slop; FP32 rounds these values and the sinks' offsets to
+// within 6e-8 of their size, so the widened tests keep every bucket the exact
+// FP64 tests would.  A bound that comes within the group's reach of half a
+// box from gc has no image common to all sinks; such a bucket is kept
+// untested.  The records (kRefineRec floats each) go to an LDS stage.
 // `w.far` reports whether any kept bucket reaches within the group's extent
-// gext of half a box from the group centre gc on some axis, i.e. whether one of
-// its particles may need the minimum image (a superset of `needs_image`, as
-// every particle lies inside its bucket's cell bound).
-constexpr int kRefineBatch = 16;
-constexpr int kRefineStageBytes = kRefineBatch * 16 * (int)sizeof(double);
+// gext of half a box from gc on some axis, i.e. whether one of its particles
+// may need the minimum image (a superset of `needs_image`, as every particle
+// lies inside its bucket's cell bound).
+constexpr int kRefineBatch = 32;
+constexpr int kRefineRec = 20;   // cell centre + half width (6), keep flag, box of balls (6), ball (4)
+constexpr int kRefineStageBytes = kRefineBatch * kRefineRec * (int)sizeof(float);
 
 template <bool SCATTER>
 __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__restrict__ nodes,
-                       const double *xi, double R, bool act, const double *gc,
-                       const double *gext, uint32_t *cand, double *stage, WalkState &w) {
+                       const double *xi, double R, double Rmax, bool act, const double *gc,
+                       const double *gext, uint32_t *cand, float *stage, WalkState &w) {
     const int lane = threadIdx.x;
     constexpr int NB = kRefineBatch;
+    float q[3];   // the sink's offset from gc
+    for (int c = 0; c < 3; ++c)
+        q[c] = (float)(per ? min_image(xi[c] - gc[c], g.L[c], g.halfL[c]) : xi[c] - gc[c]);
+    const double Rw = R * (1.0 + 1e-5) + slop;
+    const float R2 = act ? (float)(Rw * Rw) * (1.0f + 1e-6f) : -1.0f;
+    const double gmax = fmax(gext[0], fmax(gext[1], gext[2]));
     int kept = 0;
     bool far = false;
     for (int t0 = 0; t0 < w.ncand; t0 += NB) {
@@ -386,38 +409,61 @@ __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__re
         int bfar = 0;
         if (lane < nb) {
             bl = cand[t0 + lane];
-            const Node *nd = nodes + g.node0 + g.nbp + ((int64_t)bl - g.b0);
+            const Node nd = nodes[g.node0 + g.nbp + ((int64_t)bl - g.b0)];
+            float *rec = stage + lane * kRefineRec;
+            bool keep = false;
+            double smax = 0.0;
             for (int c = 0; c < 3; ++c) {
-                const double lo = nd->clo[c], hi = nd->chi[c];
-                stage[c * NB + lane] = lo;
-                stage[(3 + c) * NB + lane] = hi;
+                const double lo = nd.clo[c], hi = nd.chi[c];
                 if (per && fmax(fabs(lo - gc[c]), fabs(hi - gc[c])) + gext[c] >= 0.999 * g.halfL[c])
                     bfar = 1;
+                double cc = 0.5 * (lo + hi) - gc[c];
+                const double hw = 0.5 * (hi - lo);
+                if (per) cc = min_image(cc, g.L[c], g.halfL[c]);
+                if (!(hw >= 0.0) || (per && fabs(cc) + hw + gext[c] + Rmax >= 0.499 * g.L[c]))
+                    keep = true;
+                rec[c] = (float)cc;
+                rec[3 + c] = (float)(hw + 1e-5 * (fabs(cc) + hw + gext[c] + Rmax) + slop);
                 if (SCATTER) {
-                    stage[(6 + c) * NB + lane] = nd->blo[c];
-                    stage[(9 + c) * NB + lane] = nd->bhi[c];
-                    stage[(12 + c) * NB + lane] = nd->bc[c];
+                    double bcc = 0.5 * (nd.blo[c] + nd.bhi[c]) - gc[c];
+                    const double bw = 0.5 * (nd.bhi[c] - nd.blo[c]);
+                    if (per) bcc = min_image(bcc, g.L[c], g.halfL[c]);
+                    if (!(bw >= 0.0) || (per && fabs(bcc) + bw + gext[c] >= 0.499 * g.L[c]))
+                        keep = true;
+                    rec[8 + c] = (float)bcc;
+                    rec[11 + c] = (float)(bw + 1e-5 * (fabs(bcc) + bw + gext[c]) + slop);
+                    double sc = nd.bc[c] - gc[c];
+                    if (per) sc = min_image(sc, g.L[c], g.halfL[c]);
+                    if (per && fabs(sc) + nd.br + gext[c] >= 0.499 * g.L[c]) keep = true;
+                    rec[16 + c] = (float)sc;
+                    smax = fmax(smax, fabs(sc));
                 }
             }
-            if (SCATTER) stage[15 * NB + lane] = nd->br;
+            rec[6] = keep ? 1.0f : 0.0f;
+            if (SCATTER) {
+                if (!(nd.br >= 0.0)) rec[6] = 1.0f;
+                const double rr = nd.br + 1e-5 * (smax + nd.br + gmax) + slop;
+                rec[19] = (float)(rr * rr) * (1.0f + 1e-6f);
+            }
         }
         __syncthreads();
         for (int u = 0; u < nb; ++u) {
-            bool ok = false;
-            if (act) {
-                const double clo[3] = {stage[u], stage[NB + u], stage[2 * NB + u]};
-                const double chi[3] = {stage[3 * NB + u], stage[4 * NB + u], stage[5 * NB + u]};
-                ok = ball_box(xi, R, clo, chi, g, per, slop);
-                if (SCATTER && !ok) {
-                    const double blo[3] = {stage[6 * NB + u], stage[7 * NB + u], stage[8 * NB + u]};
-                    const double bhi[3] = {stage[9 * NB + u], stage[10 * NB + u],
-                                           stage[11 * NB + u]};
-                    const double bc[3] = {stage[12 * NB + u], stage[13 * NB + u],
-                                          stage[14 * NB + u]};
-                    ok = ball_box(xi, 0.0, blo, bhi, g, per, slop) &&
-                         point_in_ball(xi, bc, stage[15 * NB + u], g, per, slop);
-                }
+            const float *rec = stage + u * kRefineRec;
+            const V4<float> r0 = ld4(rec), r1 = ld4(rec + 4);
+            const float gx = fmaxf(fabsf(q[0] - r0.x) - r0.w, 0.0f);
+            const float gy = fmaxf(fabsf(q[1] - r0.y) - r1.x, 0.0f);
+            const float gz = fmaxf(fabsf(q[2] - r0.z) - r1.y, 0.0f);
+            bool ok = r1.z != 0.0f || fmaf(gx, gx, fmaf(gy, gy, gz * gz)) <= R2;
+            if (SCATTER) {
+                const V4<float> r2 = ld4(rec + 8), r3 = ld4(rec + 12), r4 = ld4(rec + 16);
+                const float ex = fabsf(q[0] - r2.x) - r2.w;
+                const float ey = fabsf(q[1] - r2.y) - r3.x;
+                const float ez = fabsf(q[2] - r2.z) - r3.y;
+                const float sx = q[0] - r4.x, sy = q[1] - r4.y, sz = q[2] - r4.z;
+                ok = ok || (fmaxf(ex, fmaxf(ey, ez)) <= 0.0f &&
+                            fmaf(sx, sx, fmaf(sy, sy, sz * sz)) <= r4.w);
             }
+            ok = ok && act;
             if (__any(ok)) {
                 if (lane == 0) cand[kept] = (uint32_t)__builtin_amdgcn_readlane((int)bl, u);
                 far = far || __builtin_amdgcn_readlane(bfar, u) != 0;
@@ -533,9 +579,6 @@ __device__ __forceinline__ int64_t sweep_slot(const SetGeom &g, const uint32_t *
     return j < g.p1 ? j : -1;
 }
 
-// Four values staged together so one LDS instruction moves them.
-template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
-
 // ================================================================ pair compaction
 //
 // A staged tile holds 64 candidates; a wave holds 64 sinks.  Evaluating the
@@ -627,9 +670,6 @@ __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetc
     while (produced > consumed) run(min(U * kWave, produced - consumed));
 }
 
-// Four consecutive entries of an LDS array (one 128-bit read for FP32).
-template <typename R>
-__device__ __forceinline__ V4<R> ld4(const R *p) { return *reinterpret_cast<const V4<R> *>(p); }
 
 // Square root of the pair distance: the hardware instruction in FP32 (within
 // one ulp, the mixed path's tolerance is far wider), IEEE in FP64.
@@ -701,7 +741,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     R *const ty = tx + kWave;
     R *const tz = ty + kWave;
     R *const tm = tz + kWave;
-    double *const stage = reinterpret_cast<double *>(tile_buf);
+    float *const stage = reinterpret_cast<float *>(tile_buf);
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
     __shared__ double acc0[kWave], acc1[kWave], acc2[kWave];
 
@@ -753,6 +793,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
     sp[lane] = V4<R>{qx, qy, qz, R(0)};
     acc0[lane] = 0; acc1[lane] = 0; acc2[lane] = 0;
+
     bool wrapf = false;
 
     WalkState ws{0, 0, -1, a.stack_limit, false, false};
@@ -775,7 +816,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 walk_reset(stack, ws, true, g);
                 walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
             }
-            refine<false>(g, per, slop, a.nodes, xi, Hw, act, gc, gext, cand, stage, ws);
+            refine<false>(g, per, slop, a.nodes, xi, Hw, wave_max(act ? Hw : 0.0), act, gc, gext, cand,
+                          stage, ws);
             list_complete = (ws.nstack == 0);
             need_walk = false;
             if constexpr (MIXED) wrapf = group_needs_wrap(per, g, gext, wave_max(act ? Hw : 0.0));
@@ -808,7 +850,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                     first_chunk = true;
                     continue;
                 }
-                refine<false>(g, per, slop, a.nodes, xi, Hw, act, gc, gext, cand, stage, ws);
+                refine<false>(g, per, slop, a.nodes, xi, Hw, wave_max(act ? Hw : 0.0), act, gc, gext, cand,
+                          stage, ws);
             }
             const int ntile = sweep_tiles(ws.ncand, a.B);
             for (int t = 0; t < ntile; ++t) {
@@ -976,7 +1019,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // measured 4.21 -> 3.60 ms at 2M); the FP64 kernel's 16.5 KiB admit nine
 // waves per CU.
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 2))) void k_forces(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 3))) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
@@ -992,7 +1035,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     R *const tz = ty + kWave;
     R *const th2 = tz + kWave;
     R *const tm = th2 + kWave;
-    double *const stage = reinterpret_cast<double *>(tile_buf);
+    float *const stage = reinterpret_cast<float *>(tile_buf);
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink: (x H) (v 1/H) (A c rho sigma/H^5)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
     __shared__ double acc[4][kWave];   // a_x a_y a_z du/dt
@@ -1022,6 +1065,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     const R Lf[3] = {(R)g.L[0], (R)g.L[1], (R)g.L[2]};
     const R hLf[3] = {(R)g.halfL[0], (R)g.halfL[1], (R)g.halfL[2]};
     const double Hsink_max = wave_max(act ? Hd : 0.0);
+
     R qx, qy, qz;
     if constexpr (MIXED) {
         qx = (R)(per ? min_image(xi[0] - gc[0], g.L[0], g.halfL[0]) : xi[0] - gc[0]);
@@ -1068,7 +1112,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
             walk_reset(stack, ws, true, g);
             continue;
         }
-        refine<true>(g, per, slop, a.nodes, xi, Hd, act, gc, gext, cand, stage, ws);
+        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
         const int ntile = sweep_tiles(ws.ncand, a.B);
         for (int t = 0; t < ntile; ++t) {
             int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
