@@ -3,7 +3,7 @@
 // box-of-balls and ball-of-balls combined bottom-up).
 //
 // MI355X design: instead of a top-down recursive bisection, particles are
-// ordered along a Hilbert curve (16 bits per axis, set id in the high bits) by
+// ordered along a Hilbert curve (10 bits per axis, set id in the high bits) by
 // a hand-written stable LSD radix sort, cut into buckets of B consecutive
 // particles, and an implicit binary tree (heap layout) is laid over the
 // buckets of each set.  Fixed-size runs of a space-filling order are compact
@@ -13,7 +13,10 @@
 // cells always share a face, so every bucket and every sink group stays a
 // connected, compact region.  Every node is then a contiguous particle range, as in
 // the paper, and bounds are combined level by level with one launch per
-// tree height across all sets.
+// tree height across all sets (the small top heights in one launch).
+// 10 bits per axis give 2^30 cells per set, far more than particles even at
+// 10^8 per set, so cells shared by two particles are rare and harmless (their
+// order is the caller's); the 30-bit keys sort in 4 radix passes instead of 6.
 #include "sph_internal.h"
 
 #include <cfloat>
@@ -25,7 +28,7 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kKeyBits = 16;
+constexpr int kKeyBits = 10;
 
 __device__ inline uint64_t spread3(uint64_t v) {
     v &= 0x1fffffull;
