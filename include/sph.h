@@ -21,9 +21,11 @@
  *   Every particle array in sph_particles is a caller-owned DEVICE pointer to
  *   n contiguous doubles in the caller's particle order (structure of arrays).
  *   The caller keeps them alive until the work enqueued on the stream has
- *   completed.  The context owns everything else (sorted copies, tree,
- *   counters) and reuses it: after the first call at a given n no further
- *   device allocation happens, so the step can be captured into a HIP graph.
+ *   completed.  The context owns everything else (sorted copies, tree, walk
+ *   stacks, counters; about 280 bytes per particle at buckets of 32, 320 in
+ *   mixed precision) and reuses it: after the first call at a given n no
+ *   further device allocation happens, so the step can be captured into a
+ *   HIP graph.
  *   A context is not thread-safe; use one context per stream.
  *
  * Streams
