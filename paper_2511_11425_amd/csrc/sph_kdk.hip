@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_part(int64_t n, const doubl
     sh[5][threadIdx.x] = mn;
     __syncthreads();
     for (int st = kThreads / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
+        if ((int)threadIdx.x < st) {
             for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
             sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + st]);
         }
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kRedBlocks) void k_reduce_final(const double *__res
     for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] = part[threadIdx.x * 6 + q];
     __syncthreads();
     for (int st = kRedBlocks / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
+        if ((int)threadIdx.x < st) {
             for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
             sh[5][threadIdx.x] = fmin(sh[5][threadIdx.x], sh[5][threadIdx.x + st]);
         }

@@ -344,19 +344,6 @@ __device__ __forceinline__ bool group_needs_wrap(bool per, const SetGeom &g, con
     return false;
 }
 
-__device__ __forceinline__ bool point_in_ball(const double *x, const double *c, double R,
-                                              const SetGeom &g, bool per, double slop) {
-    if (!(R >= 0.0)) return false;
-    double d2 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        double d = x[a] - c[a];
-        if (per) d = min_image(d, g.L[a], g.halfL[a]);
-        d2 += d * d;
-    }
-    double Rs = R + slop;
-    return d2 <= Rs * Rs;
-}
-
 // Four values staged together so one LDS instruction moves them.
 template <typename R> struct alignas(4 * sizeof(R)) V4 { R x, y, z, w; };
 
