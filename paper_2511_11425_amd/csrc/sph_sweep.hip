@@ -6,15 +6,17 @@
 //             sink ball-of-balls overlap the source cell bound; scatter =
 //             source box-of-balls AND ball-of-balls overlap the sink cell
 //             bound.  Up to 64 nodes are tested per step (one per lane);
-//             accepted children are pushed and accepted buckets appended to
-//             an LDS candidate list by ballot + popcount compaction.  The
-//             list holds whole buckets (Sec. 2.3.2: lists are not pruned
-//             pairwise during the walk); a per-sink refinement then drops
-//             buckets that no sink of the group needs.
-//   tiles     candidate buckets are staged 64 particles at a time into LDS;
-//             each lane (one sink) tests its distance to every staged
-//             candidate, the accepted pairs go through a small LDS ring and
-//             are evaluated one pair per lane (see "pair compaction").
+//             accepted children are pushed on the group's stack (global
+//             memory) and accepted buckets appended to an LDS candidate list
+//             by ballot + popcount compaction.  The list holds whole buckets
+//             (Sec. 2.3.2: lists are not pruned pairwise during the walk); a
+//             per-sink refinement (FP32, conservative) then drops buckets
+//             that no sink of the group needs.
+//   tiles     candidates are staged 64 at a time into LDS, each tile taking
+//             runs of 2 slots spread over the whole list; each lane (one
+//             sink) tests its distance to every staged candidate, the
+//             accepted pairs go through a small LDS ring and are evaluated
+//             one pair per lane (see "pair compaction").
 //   density   the pairs add m f, m q f' and m (2 q f' + q^2 f'') to per-sink
 //             sums (eq:Density_estimate and its H derivatives); a Halley
 //             iteration on the constant kernel mass (Sec. 2.3.3) re-scans the
