@@ -259,10 +259,14 @@ __device__ __forceinline__ void walk_reset(uint32_t *stack, WalkState &w, bool l
 }
 
 // Continue the walk until the stack is empty or the candidate list is nearly
-// full (the caller consumes it and calls again).
+// full (the caller consumes it and calls again).  The walk and the refinement
+// run at a raised wave priority: each of their steps waits on memory, and
+// letting them issue ahead of the other waves' tile arithmetic overlaps that
+// wait with it (FP64 sweeps 4 % faster at 2M; the mixed ones unchanged).
 template <bool SCATTER>
 __device__ void walk(const SetGeom &g, bool per, double slop, const Node *__restrict__ nodes,
                      const Sink &sk, uint32_t *stack, uint32_t *cand, WalkState &w) {
+    __builtin_amdgcn_s_setprio(2);
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
     if (w.lin >= 0) {
@@ -290,6 +294,7 @@ __device__ void walk(const SetGeom &g, bool per, double slop, const Node *__rest
         }
         w.nstack = w.lin < g.nb ? 1 : 0;
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         return;
     }
     while (w.nstack > 0 && w.ncand <= kCandCap - kWave) {
@@ -330,6 +335,7 @@ __device__ void walk(const SetGeom &g, bool per, double slop, const Node *__rest
         w.ncand += __popcll(m2);
         __syncthreads();
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 __device__ __forceinline__ float wrap_f(float d, float L, float hL) {
@@ -384,6 +390,7 @@ __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__re
                        const double *gext, uint32_t *cand, float *stage, WalkState &w) {
     const int lane = threadIdx.x;
     constexpr int NB = kRefineBatch;
+    __builtin_amdgcn_s_setprio(2);   // (see walk)
     float q[3];   // the sink's offset from gc
     for (int c = 0; c < 3; ++c)
         q[c] = (float)(per ? min_image(xi[c] - gc[c], g.L[c], g.halfL[c]) : xi[c] - gc[c]);
@@ -464,6 +471,7 @@ __device__ void refine(const SetGeom &g, bool per, double slop, const Node *__re
     w.ncand = kept;
     w.far = far;
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // Per-sink sums are accumulated in FP64 in both paths: the pair terms of the
