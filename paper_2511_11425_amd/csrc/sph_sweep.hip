@@ -1193,9 +1193,19 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                     const R r = pair_sqrt(r2);
                     const R Hs_ = ip.w, Hj = cv.w;
                     R Gi = 0, Gj = 0;
-                    if (r2 < Hs_ * Hs_)   // the sink's sigma / H^5 is prepared once
+                    // (the sink's sigma / H^5 is prepared once, in its record)
+                    if constexpr (K == 0) {
+                        if (r2 < Hs_ * Hs_) Gi = iq.w * shape_g<K, R>(r * iv.w, Hs_, r);
+                        if (r2 < Hj * Hj) {
+                            const R hinv = cq.x;
+                            const R h2 = hinv * hinv;
+                            Gj = sig * shape_g<K, R>(r * hinv, Hj, r) * (h2 * h2 * hinv);
+                        }
+                    } else {
+                        // the Wendland shapes vanish for q >= 1 through their
+                        // clamped (1 - q), so no branch on the support is needed
+                        // (2M mixed forces 3.41 -> 3.33 ms)
                         Gi = iq.w * shape_g<K, R>(r * iv.w, Hs_, r);
-                    if (r2 < Hj * Hj) {
                         const R hinv = cq.x;
                         const R h2 = hinv * hinv;
                         Gj = sig * shape_g<K, R>(r * hinv, Hj, r) * (h2 * h2 * hinv);
