@@ -594,6 +594,9 @@ __device__ __forceinline__ int64_t sweep_slot(const SetGeom &g, const uint32_t *
 //            contributions added to the sinks' LDS accumulators with LDS
 //            float atomics (one wave per workgroup, so the order of the adds
 //            is fixed).  The remainder is drained at the end of the tile.
+//            The sweeps use U = 1: at four or five waves per SIMD the other
+//            waves hide the fetch latency, and a second chunk's registers
+//            would spill (measured 2 % faster than U = 2).
 // Each sink then folds the tile's partial sums into its own accumulators.
 // The ring never holds more than U x 64 - 1 + 64 pairs, so the pair list
 // costs kRing x 2 bytes of LDS instead of one entry per possible pair.  The
@@ -883,7 +886,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                                                        dx, dy, dz);
                     };
                     struct PD { int s; R x, y, z, m; V4<R> si; };
-                    tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0, uint32_t b) {
+                    tile_pairs<1>(ring, [&](int k0, uint32_t b) {
 #pragma unroll
                         for (int h = 0; h < 8; h += 4) {
                             const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
@@ -1171,7 +1174,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                     return push_hit(b, r2, Hi2 > h2 ? Hi2 : h2);
                 };
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
-                tile_pairs<MIXED ? 2 : 1>(ring, [&](int k0, uint32_t b) {
+                tile_pairs<1>(ring, [&](int k0, uint32_t b) {
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
                         const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
