@@ -98,3 +98,32 @@ def test_ten_steps_mixed(sph, orc):
     assert verr < 1e-3 * dv
     assert xerr < 1e-3 * dv * t
     assert np.all(np.abs(dts[:, 0] - dts[:, 1]) <= 1e-3 * dts[:, 1])
+
+
+def test_step_after_caller_changes_h(sph, orc):
+    """The first guess of the smoothing-length iteration is the last step's H
+    extrapolated by its change; when the caller rescales H between steps the
+    guess is far off, and the step must still reach the oracle's result (the
+    root does not depend on the guess)."""
+    case = CASES[0]
+    c = si.random_cloud(case["seed"], case["n"], kernel=case["kernel"], n_ngb=case["n_ngb"],
+                        periodic=True, clumped=case["clumped"])
+    s, p = c["state"], c["params"]
+    P = sph.ParticleArrays.from_state(s)
+    ctx = sph.Context(p)
+    print("step after a caller change of H", flush=True)
+    ctx.init(P)
+    ref = orc.init(p, s)
+    ctx.step(P)
+    orc.step(p, ref)
+    P["H"].mul_(1.7)           # caller rescales H between steps
+    ref["H"] = ref["H"] * 1.7
+    ctx.step(P)
+    rep = orc.step(p, ref)
+    got = P.numpy()
+    assert abs(ctx.stats()["dt_used"] - rep["dt"]) <= 1e-12 * rep["dt"]
+    for k in ("H", "rho", "omega"):
+        assert np.max(np.abs(got[k] - ref[k]) / np.abs(ref[k])) < 1e-11, k
+    arms = np.sqrt(np.mean(ref["ax"] ** 2 + ref["ay"] ** 2 + ref["az"] ** 2))
+    for k in ("ax", "ay", "az"):
+        assert np.max(np.abs(got[k] - ref[k])) < 1e-10 * arms, k
