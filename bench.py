@@ -262,7 +262,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the sweep runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     log(f"generating workload {args.workload}")
     case = make_workload(args.workload, args.small)
