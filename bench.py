@@ -198,10 +198,15 @@ def cpu_baseline(case, seconds=15.0):
                     desc=case["desc"] + " (first set)")
     s = case["state"]
     n = len(s["x"])
-    pilot = _oracle_sample(case, min(n, 20000))
-    per_row = pilot["secs"] / pilot["rows"]
-    # three runs of about seconds / 3 each; the median is reported
-    rows = int(min(n, max(20000, seconds / 3 / max(per_row, 1e-9))))
+    # two pilots separate the fixed cost (the cell list over every particle)
+    # from the cost per row; three runs of about seconds / 3 each follow and
+    # the median is reported
+    r1, r2 = min(n, 20000), min(n, 80000)
+    p1 = _oracle_sample(case, r1)
+    p2 = _oracle_sample(case, r2) if r2 > r1 else p1
+    per_row = max((p2["secs"] - p1["secs"]) / max(r2 - r1, 1), p1["secs"] / r1 * 0.05, 1e-9)
+    fixed = max(p1["secs"] - per_row * r1, 0.0)
+    rows = int(min(n, max(r1, (seconds / 3 - fixed) / per_row)))
     runs = [_oracle_sample(case, rows, final=True) for _ in range(3)]
     return sorted(runs, key=lambda r: r["value"])[1]
 
