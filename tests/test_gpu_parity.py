@@ -288,3 +288,57 @@ def test_paused_walk_resumes(sph, orc, precision):
         assert rms_err(g[k], fref[k], arms) < (1e-12 if precision == "fp64" else 1e-4), k
     if precision == "fp64":
         assert ctx.stats()["pairs_force"] == int(fref["count"].sum())
+
+
+def degenerate_cloud():
+    """A clumped periodic cloud where 100 particles sit exactly on top of
+    others (r = 0 pairs) and ten lie on the box faces (x = 0, y just below 1)."""
+    c = si.random_cloud(21, 2000, kernel="wc4", n_ngb=80, periodic=True, clumped=True)
+    s = c["state"]
+    rng = np.random.default_rng(5)
+    dup = rng.choice(2000, 100, replace=False)
+    src = rng.choice(2000, 100, replace=False)
+    for k in ("x", "y", "z"):
+        s[k][dup] = s[k][src]
+    s["x"][:5] = 0.0
+    s["y"][5:10] = np.nextafter(1.0, 0.0)
+    return c
+
+
+def test_coincident_and_face_particles(sph, orc):
+    """Pairs at r = 0 count as neighbours and exert neither force nor heating
+    (Sec. 2.3.5 with x_ij = 0); particles on the box faces find their
+    neighbours through the minimum image.  FP64 to the usual bars, the
+    neighbour counts exactly; the mixed path finite and within its bars."""
+    c = degenerate_cloud()
+    s, p = c["state"], c["params"]
+    P = sph.ParticleArrays.from_state(s)
+    ctx = sph.Context(p)
+    print("coincident and face particles fp64", flush=True)
+    ctx.build_tree(P)
+    ctx.density(P)
+    got = P.numpy()
+    ref = orc.solve_h(p, s["x"], s["y"], s["z"], s["m"], s["H"])
+    for k in ("H", "rho", "omega"):
+        assert rel(got[k], ref[k]) < 1e-12, k
+    assert ctx.stats()["pairs_density"] == int(ref["count"].sum())
+    st, fref, Pp, cs = force_inputs(orc, c)
+    P2 = sph.ParticleArrays.from_state(st)
+    ctx.build_tree(P2)
+    ctx.forces(P2)
+    g2 = P2.numpy()
+    arms = np.sqrt(np.mean(fref["ax"] ** 2 + fref["ay"] ** 2 + fref["az"] ** 2))
+    for k in ("ax", "ay", "az"):
+        assert rms_err(g2[k], fref[k], arms) < 1e-12, k
+    durms = np.sqrt(np.mean(fref["dudt"] ** 2))
+    assert rms_err(g2["dudt"], fref["dudt"], durms) < 1e-12
+    assert ctx.stats()["pairs_force"] == int(fref["count"].sum())
+    # mixed precision on the same inputs
+    cm = sph.Context(dict(p, precision="mixed"))
+    P3 = sph.ParticleArrays.from_state(st)
+    cm.build_tree(P3)
+    cm.forces(P3)
+    g3 = P3.numpy()
+    assert all(np.all(np.isfinite(g3[k])) for k in ("ax", "ay", "az", "dudt", "dt"))
+    for k in ("ax", "ay", "az"):
+        assert rms_err(g3[k], fref[k], arms) < 1e-4, k
