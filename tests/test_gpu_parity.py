@@ -342,3 +342,37 @@ def test_coincident_and_face_particles(sph, orc):
     assert all(np.all(np.isfinite(g3[k])) for k in ("ax", "ay", "az", "dudt", "dt"))
     for k in ("ax", "ay", "az"):
         assert rms_err(g3[k], fref[k], arms) < 1e-4, k
+
+
+@pytest.mark.parametrize("n,n_ngb", [(300, 150), (400, 100)])
+def test_smoothing_length_at_the_cap(sph, orc, n, n_ngb):
+    """Few particles, many neighbours: most (or some) smoothing lengths reach
+    the cap of 0.45 of the periodic box, where every sink group's
+    neighbourhood wraps the box.  The capped particles are counted and every
+    result equals the oracle's (FP64) or stays within the mixed bars."""
+    c = si.random_cloud(31, n, kernel="m4", n_ngb=n_ngb, periodic=True, clumped=False)
+    s, p = c["state"], c["params"]
+    ref = orc.solve_h(p, s["x"], s["y"], s["z"], s["m"], s["H"])
+    print(f"H at the cap n={n} n_ngb={n_ngb}: {ref['n_noconv']} capped", flush=True)
+    for precision, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        P = sph.ParticleArrays.from_state(s)
+        ctx = sph.Context(dict(p, precision=precision))
+        ctx.build_tree(P)
+        ctx.density(P)
+        got = P.numpy()
+        st = ctx.stats()
+        assert st["n_noconv"] == ref["n_noconv"], precision
+        for k in ("H", "rho"):
+            assert rel(got[k], ref[k]) < tol, (precision, k)
+        if precision == "fp64":
+            assert st["pairs_density"] == int(ref["count"].sum())
+    st2, fref, Pp, cs = force_inputs(orc, c)
+    P2 = sph.ParticleArrays.from_state(st2)
+    ctx = sph.Context(p)
+    ctx.build_tree(P2)
+    ctx.forces(P2)
+    g2 = P2.numpy()
+    arms = np.sqrt(np.mean(fref["ax"] ** 2 + fref["ay"] ** 2 + fref["az"] ** 2))
+    for k in ("ax", "ay", "az"):
+        assert rms_err(g2[k], fref[k], arms) < 1e-12, k
+    assert ctx.stats()["pairs_force"] == int(fref["count"].sum())
