@@ -557,7 +557,8 @@ __device__ __forceinline__ int64_t slot_index(const SetGeom &g, const uint32_t *
 // neighbourhood of the group instead of 64/B adjacent buckets, so the sinks'
 // hit counts per tile are even and the compaction, whose rounds number the
 // largest count of any sink, needs about half as many rounds.  (Runs of 2
-// measured as fast as single slots and faster than runs of 4 or 8.)  An FP64
+// and 4 measure alike; single slots cost more in staging, runs of 8 more
+// compaction rounds.)  An FP64
 // tile takes the minimum-image path as soon as one of its candidates may need
 // it, which interleaved tiles of a group near the box edge nearly all would;
 // such lists (refine's `far`) keep adjacent buckets per tile (slot_index).
