@@ -51,34 +51,56 @@ def build(force: bool = False) -> str:
 _lib = None
 
 
+def configure(L):
+    """Declare the C signatures on a loaded oracle library and check its layout."""
+    dp = POINTER(c_double)
+    ip = POINTER(c_int64)
+    pp = POINTER(Params)
+    L.orc_sigma.restype = c_double
+    L.orc_sigma.argtypes = [c_int]
+    L.orc_num_threads.restype = c_int
+    L.orc_params_size.restype = c_int
+    L.orc_kernel_shape.argtypes = [c_int, c_int64, dp, dp, dp]
+    L.orc_kernel_w.argtypes = [c_int, c_int64, dp, dp, dp, dp, dp]
+    L.orc_neighbors.argtypes = [pp, c_int64, dp, dp, dp, dp, c_int, ip, ip, ip]
+    L.orc_neighbors.restype = c_int
+    L.orc_density.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, ip, c_int64, dp, dp, dp, ip]
+    L.orc_density.restype = c_int
+    L.orc_solve_h.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, ip, c_int64, dp, dp, dp, ip,
+                              POINTER(c_int32), POINTER(c_int64)]
+    L.orc_solve_h.restype = c_int
+    L.orc_eos.argtypes = [pp, c_int64, dp, dp, dp, dp]
+    L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [ip, c_int64] + [dp] * 5 + [ip]
+    L.orc_forces.restype = c_int
+    if L.orc_params_size() != ctypes.sizeof(Params):
+        raise RuntimeError("oracle parameter layout mismatch")
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(_LIB)
-        dp = POINTER(c_double)
-        ip = POINTER(c_int64)
-        pp = POINTER(Params)
-        L.orc_sigma.restype = c_double
-        L.orc_sigma.argtypes = [c_int]
-        L.orc_num_threads.restype = c_int
-        L.orc_params_size.restype = c_int
-        L.orc_kernel_shape.argtypes = [c_int, c_int64, dp, dp, dp]
-        L.orc_kernel_w.argtypes = [c_int, c_int64, dp, dp, dp, dp, dp]
-        L.orc_neighbors.argtypes = [pp, c_int64, dp, dp, dp, dp, c_int, ip, ip, ip]
-        L.orc_neighbors.restype = c_int
-        L.orc_density.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, ip, c_int64, dp, dp, dp, ip]
-        L.orc_density.restype = c_int
-        L.orc_solve_h.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, ip, c_int64, dp, dp, dp, ip,
-                                  POINTER(c_int32), POINTER(c_int64)]
-        L.orc_solve_h.restype = c_int
-        L.orc_eos.argtypes = [pp, c_int64, dp, dp, dp, dp]
-        L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [ip, c_int64] + [dp] * 5 + [ip]
-        L.orc_forces.restype = c_int
-        if L.orc_params_size() != ctypes.sizeof(Params):
-            raise RuntimeError("oracle parameter layout mismatch")
-        _lib = L
+        _lib = configure(ctypes.CDLL(_LIB))
     return _lib
+
+
+def source_text() -> str:
+    """The oracle's C source (tests compile altered copies of it to show that
+    their checks catch a planted mistake)."""
+    with open(_SRC) as f:
+        return f.read()
+
+
+def compile_variant(src: str, path: str):
+    """Compile C source `src` with the oracle's flags into `path` and load it."""
+    cpath = path + ".c"
+    with open(cpath, "w") as f:
+        f.write(src)
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", cpath, "-o", path, "-lm"]
+    subprocess.check_call(cmd)
+    return configure(ctypes.CDLL(path))
 
 
 class Params(ctypes.Structure):
