@@ -36,10 +36,19 @@
  *
  * Errors
  *   Argument errors return SPH_ERR_INVALID synchronously and enqueue nothing.
- *   HIP runtime errors return SPH_ERR_HIP.  Conditions found on the device
- *   (smoothing-length cap reached, a walk stack overflow) are counted in
- *   device counters and reported by sph_get_stats.  sph_last_error() gives a
- *   text for the last failing call.  No C++ exception crosses this interface.
+ *   HIP runtime errors return SPH_ERR_HIP.  Conditions found on the device go
+ *   to a device status word, cleared at the start of every call:
+ *     SPH_ERR_NOCONV     a smoothing-length iteration stopped at nr_maxit;
+ *     SPH_ERR_NONFINITE  a non-finite H, rho, Omega, a, du/dt or dt.
+ *   The status of a call is surfaced (1) by sph_get_stats (sph_stats.status,
+ *   with the counts), which synchronises, and (2) by the NEXT call on the
+ *   context once the device has finished the call that set it: that next call
+ *   then returns the status and enqueues nothing (the status is reported
+ *   once; calling again proceeds).  A call never waits for the device to
+ *   learn the status.  Conditions that are not errors (H held at the cap
+ *   h_max, a walk that fell back to the linear bucket test) are counted in
+ *   sph_stats only.  sph_last_error() gives a text for the last failing call.
+ *   No C++ exception crosses this interface.
  */
 #ifndef SPH_MI355X_H
 #define SPH_MI355X_H
@@ -58,8 +67,11 @@ typedef enum {
     SPH_ERR_OOM = 2,      /* device allocation failed */
     SPH_ERR_HIP = 3,      /* HIP runtime error */
     SPH_ERR_CAPACITY = 4, /* output buffer too small (see sph_neighbors) */
-    SPH_ERR_NOCONV = 5,   /* reserved: reported through sph_stats.n_noconv */
-    SPH_ERR_STATE = 6     /* call out of order (e.g. density before a tree) */
+    SPH_ERR_NOCONV = 5,   /* the smoothing-length iteration of some particle reached
+                             nr_maxit without converging (device status word) */
+    SPH_ERR_STATE = 6,    /* call out of order (e.g. density before a tree) */
+    SPH_ERR_NONFINITE = 7 /* a NaN or infinity in H, rho, Omega, a, du/dt or dt
+                             (device status word) */
 } sph_status;
 
 enum { SPH_KERNEL_M4 = 0, SPH_KERNEL_WC2 = 1, SPH_KERNEL_WC4 = 2, SPH_KERNEL_WC6 = 3 };
@@ -123,8 +135,8 @@ typedef struct {
     int64_t nr_scans;             /* density scans summed over sink groups */
     int64_t n_noconv;             /* particles whose H hit the cap or the iteration limit */
     int64_t n_rewalk;             /* sink groups re-walked because H outgrew the search radius */
-    int64_t n_overflow;           /* sink groups whose tree walk outgrew the LDS stack and
-                                     fell back to testing every bucket (results stay exact) */
+    int64_t n_overflow;           /* sink groups whose tree walk outgrew its stack and fell
+                                     back to testing every bucket (results stay exact) */
     double momentum[3];           /* sum m v after the last step (FP64) */
     double e_kin, e_int;          /* sum m v^2/2, sum m u after the last step (FP64) */
     double dt_next;               /* min_i dt_i from the last force pass, capped by dt_max */
@@ -135,6 +147,13 @@ typedef struct {
     double t_density_ms;          /* tree build, density kernel, force kernel and the whole */
     double t_forces_ms;           /* call (HIP events on the call's stream); -1 when the */
     double t_total_ms;            /* phase did not run or timing is off */
+    int64_t n_iter_limit;         /* particles whose iteration stopped at nr_maxit */
+    int64_t n_nonfinite;          /* particles with a non-finite output */
+    int64_t n_retest;             /* mixed path: pairs near a neighbour-set boundary whose
+                                     membership was decided by an FP64 re-test */
+    int32_t status;               /* device status word of the last call: SPH_OK,
+                                     SPH_ERR_NOCONV or SPH_ERR_NONFINITE */
+    int32_t reserved_;
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -218,7 +237,9 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
  * Timing is skipped inside graph capture. */
 sph_status sph_set_timing(sph_ctx *ctx, int32_t enable);
 
-/* Synchronises the context's last stream and copies the counters. */
+/* Synchronises the context's last stream and copies the counters and the
+ * status word of the last call (which is then not reported again by the next
+ * call).  Returns SPH_OK whenever the copy succeeds. */
 sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out);
 
 #ifdef __cplusplus

@@ -204,6 +204,18 @@ def neighbors(params: dict, x, y, z, H, mode: int = 0):
     return offsets, idx[: int(offsets[-1])]
 
 
+def neighbor_counts(params: dict, x, y, z, H, mode: int = 0):
+    """|G_i| (mode 0) or |F_i| (mode 1) per particle, without the sets."""
+    P = make_params(params)
+    n = len(x)
+    arrs = [_d(v) for v in (x, y, z, H)]
+    counts, cp = _i(np.zeros(n, dtype=np.int64))
+    rc = lib().orc_neighbors(ctypes.byref(P), n, *[a[1] for a in arrs], mode, cp, None, None)
+    if rc != 0:
+        raise RuntimeError("oracle neighbour search failed")
+    return counts
+
+
 def _rows(rows, n):
     if rows is None:
         return None, None, n

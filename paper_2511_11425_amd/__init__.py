@@ -21,7 +21,8 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-SPH_OK, SPH_ERR_INVALID, SPH_ERR_OOM, SPH_ERR_HIP, SPH_ERR_CAPACITY, SPH_ERR_NOCONV, SPH_ERR_STATE = range(7)
+(SPH_OK, SPH_ERR_INVALID, SPH_ERR_OOM, SPH_ERR_HIP, SPH_ERR_CAPACITY, SPH_ERR_NOCONV, SPH_ERR_STATE,
+ SPH_ERR_NONFINITE) = range(8)
 KERNELS = {"m4": 0, "wc2": 1, "wc4": 2, "wc6": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 EOS = {"ideal": 0, "stiffened": 1}
@@ -64,7 +65,8 @@ class Stats(ctypes.Structure):
         ("e_int", c_double), ("dt_next", c_double), ("dt_used", c_double),
         ("pairs_density_total", c_int64), ("pairs_force_total", c_int64),
         ("t_tree_ms", c_double), ("t_density_ms", c_double), ("t_forces_ms", c_double),
-        ("t_total_ms", c_double),
+        ("t_total_ms", c_double), ("n_iter_limit", c_int64), ("n_nonfinite", c_int64),
+        ("n_retest", c_int64), ("status", c_int32), ("reserved_", c_int32),
     ]
 
 

@@ -58,6 +58,8 @@ void free_all(Ctx &c) {
     c.allocs.clear();
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
     if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
+    if (c.h_flags) { (void)hipHostFree(c.h_flags); c.h_flags = nullptr; }
+    c.status_pending = false;
     c.n = 0;
     c.have_tree = false;
     c.have_forces = false;
@@ -90,19 +92,25 @@ bool valid_params(const sph_params *p, std::string &why) {
     return true;
 }
 
-// Topology of buckets, groups and tree nodes for the current n and bucket size.
-sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
-    Ctx &c = x->c;
-    if (c.n == n && c.allocs.size() > 0 && c.topo_bucket == c.bucket) return SPH_OK;
-    free_all(c);
-    const int B = c.bucket;
-    const int ns = c.nsets;
-    std::vector<SetGeom> sets(ns);
+// Topology of buckets, groups and tree nodes for n particles and bucket size B.
+struct Topology {
+    std::vector<SetGeom> sets;
     std::vector<int32_t> grp_set, bkt_set;
+    std::vector<int64_t> pref;        // (max_depth+1) x (nsets+1): prefix of nodes per height
+    std::vector<int64_t> level_total;
+    int64_t nbuckets = 0, ngroups = 0, nnodes = 0;
+    int max_depth = 0;
+};
+
+bool make_topology(const Ctx &c, int B, Topology &t, std::string &why) {
+    const int ns = c.nsets;
+    t.sets.assign(ns, SetGeom{});
+    t.grp_set.clear();
+    t.bkt_set.clear();
     int64_t b0 = 0, g0 = 0, node0 = 0;
     int max_depth = 0;
     for (int q = 0; q < ns; ++q) {
-        SetGeom &g = sets[q];
+        SetGeom &g = t.sets[q];
         g.p0 = c.set_off[q];
         g.p1 = c.set_off[q + 1];
         int64_t np = g.p1 - g.p0;
@@ -110,7 +118,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
         int64_t nbp = 1;
         int depth = 0;
         while (nbp < nb) { nbp <<= 1; ++depth; }
-        if (nbp > (int64_t)1 << 30) return fail(x, SPH_ERR_INVALID, "set too large");
+        if (nbp > (int64_t)1 << 30) { why = "set too large"; return false; }
         g.nb = (int32_t)nb;
         g.nbp = (int32_t)nbp;
         g.depth = depth;
@@ -125,29 +133,82 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
             g.halfL[a] = 0.5 * g.L[a];
         }
         int64_t ng = (np + kGroup - 1) / kGroup;
-        for (int64_t k = 0; k < ng; ++k) grp_set.push_back(q);
-        for (int64_t k = 0; k < nb; ++k) bkt_set.push_back(q);
+        for (int64_t k = 0; k < ng; ++k) t.grp_set.push_back(q);
+        for (int64_t k = 0; k < nb; ++k) t.bkt_set.push_back(q);
         b0 += nb;
         g0 += ng;
         node0 += 2 * nbp;
         max_depth = std::max(max_depth, depth);
     }
-    c.nbuckets = b0;
-    c.ngroups = g0;
-    c.nnodes = node0;
-    c.max_depth = max_depth;
+    t.nbuckets = b0;
+    t.ngroups = g0;
+    t.nnodes = node0;
+    t.max_depth = max_depth;
     // nodes per height d: nbp >> d for sets with depth >= d
-    std::vector<int64_t> pref((size_t)(max_depth + 1) * (ns + 1), 0);
-    c.level_total.assign(max_depth + 1, 0);
+    t.pref.assign((size_t)(max_depth + 1) * (ns + 1), 0);
+    t.level_total.assign(max_depth + 1, 0);
     for (int d = 0; d <= max_depth; ++d) {
         int64_t acc = 0;
         for (int q = 0; q < ns; ++q) {
-            pref[(size_t)d * (ns + 1) + q] = acc;
-            if (sets[q].depth >= d && sets[q].nb > 0) acc += (int64_t)(sets[q].nbp >> d);
+            t.pref[(size_t)d * (ns + 1) + q] = acc;
+            if (t.sets[q].depth >= d && t.sets[q].nb > 0) acc += (int64_t)(t.sets[q].nbp >> d);
         }
-        pref[(size_t)d * (ns + 1) + ns] = acc;
-        c.level_total[d] = acc;
+        t.pref[(size_t)d * (ns + 1) + ns] = acc;
+        t.level_total[d] = acc;
     }
+    return true;
+}
+
+// Copies the topology of the context's current bucket size to the device
+// (the allocation holds the largest one, that of the smallest bucket size).
+sph_status upload_topology(sph_ctx *x, const Topology &t, hipStream_t s) {
+    Ctx &c = x->c;
+    const int ns = c.nsets;
+    c.nbuckets = t.nbuckets;
+    c.ngroups = t.ngroups;
+    c.nnodes = t.nnodes;
+    c.max_depth = t.max_depth;
+    c.level_total = t.level_total;
+    HIPCHK(x, hipMemcpyAsync(c.d_sets, t.sets.data(), sizeof(SetGeom) * ns, hipMemcpyHostToDevice, s),
+           "sets");
+    if (!t.grp_set.empty())
+        HIPCHK(x, hipMemcpyAsync(c.d_grp_set, t.grp_set.data(), sizeof(int32_t) * t.grp_set.size(),
+                                 hipMemcpyHostToDevice, s), "groups");
+    if (!t.bkt_set.empty())
+        HIPCHK(x, hipMemcpyAsync(c.d_bkt_set, t.bkt_set.data(), sizeof(int32_t) * t.bkt_set.size(),
+                                 hipMemcpyHostToDevice, s), "buckets");
+    HIPCHK(x, hipMemcpyAsync(c.d_level_pref, t.pref.data(), sizeof(int64_t) * t.pref.size(),
+                             hipMemcpyHostToDevice, s), "levels");
+    HIPCHK(x, launch_init_nodes(&c, s), "init nodes");
+    // host pages of the topology vectors must outlive the copies
+    HIPCHK(x, hipStreamSynchronize(s), "topology sync");
+    c.topo_bucket = c.bucket;
+    c.have_tree = false;
+    c.have_forces = false;
+    return SPH_OK;
+}
+
+// Device memory for n particles.  Every bucket-size-dependent array is sized
+// for the smallest bucket size (8), so a change of the bucket size (the
+// autotuner's trials) only rewrites the topology: after the first call at a
+// given n nothing is allocated.
+sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
+    Ctx &c = x->c;
+    std::string why;
+    Topology t;
+    if (c.n == n && c.allocs.size() > 0) {
+        if (c.topo_bucket == c.bucket) return SPH_OK;
+        if (!make_topology(c, c.bucket, t, why)) return fail(x, SPH_ERR_INVALID, "set too large");
+        return upload_topology(x, t, s);
+    }
+    free_all(c);
+    const int ns = c.nsets;
+    Topology tmax;   // the largest topology (bucket size 8) sizes the allocation
+    if (!make_topology(c, 8, tmax, why) || !make_topology(c, c.bucket, t, why))
+        return fail(x, SPH_ERR_INVALID, "set too large");
+    const int64_t cap_buckets = tmax.nbuckets, cap_nodes = tmax.nnodes;
+    const size_t cap_pref = tmax.pref.size();
+    c.ngroups = t.ngroups;
     c.set_bits = 0;
     while ((1 << c.set_bits) < ns) ++c.set_bits;
     int key_bits = 3 * key_bits_per_axis() + c.set_bits;
@@ -160,9 +221,9 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     const char *what = "";
 #define A(ptr, cnt) if (e == hipSuccess) { what = #ptr; e = dalloc(c, &(ptr), (cnt)); }
     A(c.d_sets, ns);
-    A(c.d_grp_set, grp_set.size());
-    A(c.d_bkt_set, bkt_set.size());
-    A(c.d_level_pref, pref.size());
+    A(c.d_grp_set, t.grp_set.size());
+    A(c.d_bkt_set, cap_buckets);
+    A(c.d_level_pref, cap_pref);
     A(c.d_key[0], n); A(c.d_key[1], n);
     A(c.d_perm[0], n); A(c.d_perm[1], n);
     A(c.d_hist, 2 * 256 * std::max<int64_t>(c.sort_blocks, 1));  // int64 view
@@ -172,9 +233,10 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.rhos, n); A(c.oms, n); A(c.As, n); A(c.css, n); A(c.Ps, n);
     if (c.prm.precision == SPH_PREC_MIXED) { A(c.frec1, 4 * n); A(c.frec2, 4 * n); A(c.fm, n); }
     A(c.axs, n); A(c.ays, n); A(c.azs, n); A(c.dus, n); A(c.dts, n);
-    A(c.nodes, c.nnodes);
+    A(c.nodes, cap_nodes);
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
     A(c.hprev, n);
+    A(c.d_h0, n);
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
@@ -189,27 +251,20 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
         return SPH_ERR_OOM;
     }
     if (hipHostMalloc((void **)&c.h_cnt, sizeof(unsigned long long) * C_NCOUNTERS) != hipSuccess ||
-        hipHostMalloc((void **)&c.h_rep, sizeof(StepReport)) != hipSuccess) {
+        hipHostMalloc((void **)&c.h_rep, sizeof(StepReport)) != hipSuccess ||
+        hipHostMalloc((void **)&c.h_flags, 2 * sizeof(unsigned long long)) != hipSuccess) {
         free_all(c);
         return fail(x, SPH_ERR_OOM, "pinned allocation failed");
     }
-    HIPCHK(x, hipMemcpyAsync(c.d_sets, sets.data(), sizeof(SetGeom) * ns, hipMemcpyHostToDevice, s), "sets");
-    if (!grp_set.empty())
-        HIPCHK(x, hipMemcpyAsync(c.d_grp_set, grp_set.data(), sizeof(int32_t) * grp_set.size(),
-                                 hipMemcpyHostToDevice, s), "groups");
-    if (!bkt_set.empty())
-        HIPCHK(x, hipMemcpyAsync(c.d_bkt_set, bkt_set.data(), sizeof(int32_t) * bkt_set.size(),
-                                 hipMemcpyHostToDevice, s), "buckets");
-    HIPCHK(x, hipMemcpyAsync(c.d_level_pref, pref.data(), sizeof(int64_t) * pref.size(),
-                             hipMemcpyHostToDevice, s), "levels");
-    HIPCHK(x, launch_init_nodes(&c, s), "init nodes");
+    c.h_flags[0] = c.h_flags[1] = 0;
+    if (!c.status_ev)
+        HIPCHK(x, hipEventCreateWithFlags(&c.status_ev, hipEventDisableTiming), "status event");
     HIPCHK(x, launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s), "counters");
     HIPCHK(x, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_rep),
                               sizeof(StepReport) / 8, 0ull, s), "report");
-    // host pages of the metadata vectors must outlive the copies
-    HIPCHK(x, hipStreamSynchronize(s), "setup sync");
+    sph_status st = upload_topology(x, t, s);
+    if (st != SPH_OK) return st;
     c.n = n;
-    c.topo_bucket = c.bucket;
     return SPH_OK;
 }
 
@@ -222,6 +277,41 @@ sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs, int
                     !p->dudt || !p->dt))
         return fail(x, SPH_ERR_INVALID, "an output array is NULL");
     return SPH_OK;
+}
+
+// The device status word of a finished call, as an sph_status.
+sph_status flags_status(const unsigned long long *f) {
+    if (f[1]) return SPH_ERR_NONFINITE;
+    if (f[0]) return SPH_ERR_NOCONV;
+    return SPH_OK;
+}
+
+// Start of a call: the status of the previous call, once the device has
+// finished it (never waits).  A non-OK status is returned by this call, which
+// then enqueues nothing; it is reported once.
+sph_status take_status(sph_ctx *x) {
+    Ctx &c = x->c;
+    if (!c.status_pending || !c.status_ev) return SPH_OK;
+    if (hipEventQuery(c.status_ev) != hipSuccess) return SPH_OK;   // not finished yet
+    c.status_pending = false;
+    const sph_status st = flags_status(c.h_flags);
+    if (st == SPH_ERR_NOCONV)
+        return fail(x, st, "the previous call left a smoothing-length iteration at nr_maxit");
+    if (st == SPH_ERR_NONFINITE)
+        return fail(x, st, "the previous call produced a non-finite result");
+    return SPH_OK;
+}
+
+// End of an enqueuing call: the status word goes to pinned memory behind the
+// call's work, followed by the status event (skipped while capturing a graph;
+// sph_graph_launch posts it after the replay).
+hipError_t post_status(Ctx &c, hipStream_t s) {
+    if (c.capturing || !c.h_flags || !c.status_ev) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(c.h_flags, c.d_cnt + C_ITERLIM, 2 * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(c.status_ev, s);
+    if (e == hipSuccess) c.status_pending = true;
+    return e;
 }
 
 hipError_t reset_counters(Ctx &c, hipStream_t s) {
@@ -377,6 +467,7 @@ void sph_destroy(sph_ctx *ctx) {
     (void)hipDeviceSynchronize();
     free_all(ctx->c);
     free_events(ctx->c);
+    if (ctx->c.status_ev) (void)hipEventDestroy(ctx->c.status_ev);
     delete ctx;
 }
 
@@ -385,6 +476,8 @@ sph_status sph_build_tree(sph_ctx *ctx, const sph_particles *p, int64_t n, void 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
     sph_status st = check_particles(ctx, p, false, n);
+    if (st != SPH_OK) return st;
+    st = take_status(ctx);
     if (st != SPH_OK) return st;
     if (n < 0 || n > ((int64_t)1 << 31) - 1) return fail(ctx, SPH_ERR_INVALID, "bad n");
     if (c.nsets == 1) {
@@ -409,6 +502,10 @@ sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int
     if (!offsets || !needed || (mode != SPH_MODE_GATHER && mode != SPH_MODE_FORCE))
         return fail(ctx, SPH_ERR_INVALID, "bad neighbour arguments");
     (void)p;
+    {
+        sph_status st = take_status(ctx);
+        if (st != SPH_OK) return st;
+    }
     c.last_stream = s;
     HIPCHK(ctx, reset_counters(c, s), "counters");
     // counts into offsets[0..n-1], offsets[n] = 0, then exclusive scan in place
@@ -441,10 +538,13 @@ sph_status sph_density(sph_ctx *ctx, sph_particles *p, void *stream) {
     if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
     sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
+    st = take_status(ctx);
+    if (st != SPH_OK) return st;
     c.last_stream = s;
     HIPCHK(ctx, reset_counters(c, s), "counters");
     st = do_density(ctx, p, s);
     mark(&c, E_END, s);
+    if (st == SPH_OK) HIPCHK(ctx, post_status(c, s), "status");
     return st;
 }
 
@@ -455,6 +555,8 @@ sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream) {
     if (!c.have_tree) return fail(ctx, SPH_ERR_STATE, "no tree: call sph_build_tree first");
     sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
+    st = take_status(ctx);
+    if (st != SPH_OK) return st;
     c.last_stream = s;
     HIPCHK(ctx, reset_counters(c, s), "counters");
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, true, s);
@@ -462,6 +564,7 @@ sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream) {
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
     HIPCHK(ctx, launch_set_dtnext(&c, p, s), "set dt");
     mark(&c, E_END, s);
+    HIPCHK(ctx, post_status(c, s), "status");
     c.have_forces = true;
     return SPH_OK;
 }
@@ -472,7 +575,7 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     Ctx &c = ctx->c;
     sph_status st = check_particles(ctx, p, true, n);
     if (st != SPH_OK) return st;
-    st = sph_build_tree(ctx, p, n, stream);
+    st = sph_build_tree(ctx, p, n, stream);   // (takes the previous status)
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s), "counters");
     HIPCHK(ctx, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.hprev), c.n, 0ull, s),
@@ -484,6 +587,7 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
     HIPCHK(ctx, launch_set_dtnext(&c, p, s), "set dt");
     mark(&c, E_END, s);
+    HIPCHK(ctx, post_status(c, s), "status");
     c.have_forces = true;
     return SPH_OK;
 }
@@ -496,8 +600,12 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream) {
     sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     if (!(dt == dt)) return fail(ctx, SPH_ERR_INVALID, "dt is NaN");
+    st = take_status(ctx);
+    if (st != SPH_OK) return st;
     c.last_stream = s;
-    return do_step(ctx, p, dt, s);
+    st = do_step(ctx, p, dt, s);
+    if (st == SPH_OK) HIPCHK(ctx, post_status(c, s), "status");
+    return st;
 }
 
 sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream) {
@@ -508,6 +616,8 @@ sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, voi
     sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     if (!s) return fail(ctx, SPH_ERR_INVALID, "graph capture needs a non-null stream");
+    st = take_status(ctx);
+    if (st != SPH_OK) return st;
     if (c.graph_exec) { (void)hipGraphExecDestroy(c.graph_exec); c.graph_exec = nullptr; }
     if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
     HIPCHK(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -528,8 +638,11 @@ sph_status sph_graph_launch(sph_ctx *ctx, void *stream) {
     Ctx &c = ctx->c;
     if (!c.graph_exec) return fail(ctx, SPH_ERR_STATE, "no captured graph");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    sph_status st = take_status(ctx);
+    if (st != SPH_OK) return st;
     c.last_stream = s;
     HIPCHK(ctx, hipGraphLaunch(c.graph_exec, s), "graph launch");
+    HIPCHK(ctx, post_status(c, s), "status");
     return SPH_OK;
 }
 
@@ -559,6 +672,11 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->dt_used = c.h_rep->dt_used;
     out->pairs_density_total = (int64_t)c.h_cnt[C_PAIRS_D_TOT];
     out->pairs_force_total = (int64_t)c.h_cnt[C_PAIRS_F_TOT];
+    out->n_iter_limit = (int64_t)c.h_cnt[C_ITERLIM];
+    out->n_nonfinite = (int64_t)c.h_cnt[C_NONFINITE];
+    out->n_retest = (int64_t)c.h_cnt[C_RETEST];
+    out->status = (int32_t)flags_status(&c.h_cnt[C_ITERLIM]);
+    c.status_pending = false;   // reported here, not again by the next call
     auto span = [&](int a, int b) -> double {
         if (!((c.ev_mask >> a) & 1u) || !((c.ev_mask >> b) & 1u)) return -1.0;
         float ms = -1.0f;
@@ -593,10 +711,14 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
         return fail(ctx, SPH_ERR_STATE, "sph_autotune needs a previous sph_build_tree or sph_init");
     sph_status st = check_particles(ctx, p, true, n);
     if (st != SPH_OK) return st;
+    st = take_status(ctx);
+    if (st != SPH_OK) return st;
     if (n == 0) { *bucket = c.bucket; return SPH_OK; }
-    // every trial starts from the same first guess of H
-    double *H0 = nullptr;
-    HIPCHK(ctx, hipMalloc(&H0, sizeof(double) * n), "autotune scratch");
+    // every trial starts from the same first guess of H (kept in the context's
+    // scratch column, so the trials allocate nothing)
+    st = setup(ctx, n, s);
+    if (st != SPH_OK) return st;
+    double *const H0 = c.d_h0;
     hipError_t e = hipMemcpyAsync(H0, p->H, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
     const bool timing = c.timing;
     st = sph_set_timing(ctx, 1);
@@ -623,7 +745,6 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
         if (e == hipSuccess) st = sph_init(ctx, p, n, stream);
     }
     (void)hipStreamSynchronize(s);
-    (void)hipFree(H0);
     c.timing = timing;
     if (e != hipSuccess) return hip_fail(ctx, e, "autotune");
     if (st != SPH_OK) return st;

@@ -24,6 +24,8 @@ constexpr int kMaxRow = 4096;      // longest neighbour row sph_neighbors can so
 enum Counter {
     C_PAIRS_D = 0, C_PAIRS_F, C_CAND_D, C_CAND_F, C_NR_ITER_MAX, C_NR_SCANS,
     C_NOCONV, C_REWALK, C_OVERFLOW, C_ROWLONG,
+    C_ITERLIM, C_NONFINITE,               // the status word (adjacent: copied together)
+    C_RETEST,                             // mixed pairs re-tested in FP64 (exact membership)
     C_NTRANSIENT,                         // counters above are cleared by every call
     C_PAIRS_D_TOT = C_NTRANSIENT,         // running totals since the context was made
     C_PAIRS_F_TOT,
@@ -111,6 +113,7 @@ struct Ctx {
     // predictor scratch (caller order) for the step
     double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *upred = nullptr;
     double *hprev = nullptr;   // caller order: converged H of the step before (0 = none)
+    double *d_h0 = nullptr;    // caller order: the autotuner's copy of the first guess of H
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 
     // scan scratch
@@ -125,6 +128,12 @@ struct Ctx {
     double *d_part = nullptr;       // reduction partials
     unsigned long long *h_cnt = nullptr; // pinned host mirrors
     StepReport *h_rep = nullptr;
+    // status word of the last call: C_ITERLIM and C_NONFINITE copied into
+    // pinned memory at the end of every enqueuing call, then status_ev; the
+    // next call reads them once the event has completed (never waits for it)
+    unsigned long long *h_flags = nullptr;
+    hipEvent_t status_ev = nullptr;
+    bool status_pending = false;
 
     // phase timing (hipEvents on the call's stream; off during graph capture)
     bool timing = false;

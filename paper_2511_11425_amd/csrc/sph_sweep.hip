@@ -600,11 +600,12 @@ __device__ __forceinline__ int64_t sweep_slot(const SetGeom &g, const uint32_t *
 //            would spill (measured 2 % faster than U = 2).
 // Each sink then folds the tile's partial sums into its own accumulators.
 // The ring never holds more than U x 64 - 1 + 64 pairs, so the pair list
-// costs kRing x 2 bytes of LDS instead of one entry per possible pair.  The
-// workgroup is one wave, whose LDS instructions execute in issue order, so
-// ring writes and reads need only a compiler-level ordering point (a
-// workgroup barrier would also wait for every outstanding LDS atomic).
-constexpr int kRing = 256;
+// costs kRing x 2 bytes of LDS instead of one entry per possible pair (U = 1:
+// 127 pending pairs at most, so 128 entries).  The workgroup is one wave,
+// whose LDS instructions execute in issue order, so ring writes and reads
+// need only a compiler-level ordering point (a workgroup barrier would also
+// wait for every outstanding LDS atomic).
+constexpr int kRing = 128;
 
 // Hit bits are collected most significant first: `push_hit(acc, a, b)` is
 // 2 acc + (a < b), one compare whose lane mask is the carry-in of one add, in
@@ -624,11 +625,19 @@ __device__ __forceinline__ uint32_t push_hit(uint32_t acc, double a, double b) {
 // `hit8(k0, acc)` pushes the hits of candidates k0..k0+7 of this lane, in
 // that order, onto acc (push_hit); candidate c of the tile ends at bit 63 - c
 // of the lane's mask.  `fetch(s, k)` loads the operands of pair (sink s,
-// candidate k) and `apply(d, valid)` adds its contributions when `valid`.
-template <int U, class Hit8, class Fetch, class Apply>
+// candidate k) and `apply(d, valid, decided)` adds its contributions when
+// `valid`; with `decided` false it may instead return true ("defer"): the
+// pair lies in the band where only an FP64 test decides membership (mixed
+// path).  Deferred pairs of a chunk are compacted into the ring slots that
+// chunk has just consumed, `exact(s, k, act)` decides each of them (lanes
+// with `act`; called by the whole wave), and those
+// inside are applied again with `decided` true.  This rare path stays out of
+// the hot pair terms, whose register budget it would otherwise share.
+template <int U, class Hit8, class Fetch, class Apply, class Exact>
 __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetch, Apply apply,
-                                           int &hits) {
+                                           Exact exact, int &hits) {
     static_assert(U * kWave + kWave <= kRing, "pair ring too small");
+    static_assert(U == 1, "deferred pairs reuse the slots of a single chunk");
     const int lane = threadIdx.x;
     uint32_t first = 0, second = 0;   // candidates 0..31, 32..63
 #pragma unroll 1
@@ -638,17 +647,24 @@ __device__ __forceinline__ void tile_pairs(uint16_t *ring, Hit8 hit8, Fetch fetc
     uint64_t m = ((uint64_t)first << 32) | second;
     hits += __popcll(m);
     int produced = 0, consumed = 0;
-    auto run = [&](int n) {   // pairs consumed .. consumed + n - 1, n <= U * 64
-        decltype(fetch(0, 0)) d[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = u * kWave + lane;
-            const uint16_t p = ring[(consumed + (t < n ? t : 0)) & (kRing - 1)];
-            d[u] = fetch((int)(p >> 6), (int)(p & 63));
+    auto run = [&](int n) {   // pairs consumed .. consumed + n - 1, n <= 64
+        const uint16_t p = ring[(consumed + (lane < n ? lane : 0)) & (kRing - 1)];
+        const bool defer = apply(fetch((int)(p >> 6), (int)(p & 63)), lane < n, false);
+        const uint64_t bm = __ballot(defer);
+        if (bm != 0ull) {
+            __builtin_amdgcn_wave_barrier();
+            if (defer)
+                ring[__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bm,
+                                                                         (uint32_t)consumed)) &
+                     (kRing - 1)] = p;
+            __builtin_amdgcn_wave_barrier();
+            const int nb = __popcll(bm);
+            const uint16_t q = ring[(consumed + (lane < nb ? lane : 0)) & (kRing - 1)];
+            const bool in = exact((int)(q >> 6), (int)(q & 63), lane < nb);
+            apply(fetch((int)(q >> 6), (int)(q & 63)), in, true);
+            __builtin_amdgcn_wave_barrier();
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (u == 0 || u * kWave < n) apply(d[u], u * kWave + lane < n);
         consumed += n;
     };
     for (;;) {
@@ -709,6 +725,45 @@ __device__ __forceinline__ R pair_r2(R xk, R yk, R zk, R xi, R yi, R zi, bool pe
     }
 }
 
+// ================================================================ exact membership (mixed path)
+//
+// The mixed path decides r^2 < T (T = H_i^2 for the gather set, max(H_i,
+// H_j)^2 for the force set) in FP32 on coordinates relative to the group
+// centre gc, so near the boundary its answer may differ from the FP64 one
+// that defines the sets.  Bound of the difference: with A = x_j - gc and
+// B = x_i - gc (each rounded once to FP32) and t = A - B, every FP32
+// difference d has |d - t| <= u (|A| + |B| + |t|) per axis (u = 2^-24), and
+// near the boundary |A| <= |B| + sqrt(T), |B| <= G (the group's largest
+// offset from gc), so |d^2 - t^2| <= 2 u sqrt(T) |E| + 3 u T with
+// |E| <= 2 sqrt(3) (2 G + sqrt(T)) (plus sqrt(3) L when the FP32 difference is
+// re-wrapped by a box length L).  Relative to T, with sqrt(T) >= Hmin (the
+// smallest sink H of the group), the error stays below
+//   beta_r = u (4 sqrt(3) (2 G/Hmin + 1 + L/Hmin) + 3);
+// `guard_band` returns band = 2 beta_r plus 16 u for the roundings of the
+// thresholds themselves.  The FP32 test then accepts r^2 < T (1 + band), a
+// superset of the FP64 set, and the interaction re-tests in FP64 every
+// accepted pair with r >= sqrt(T) (1 - band): exactly the FP64 sets, at the
+// cost of a few FP64 tests per thousand sinks.
+__device__ __forceinline__ double guard_band(double G, double Hmin, double Lwrap) {
+    const double u = 0x1p-24;
+    return 2.0 * u * (4.0 * 1.7320508075688772 * ((2.0 * G + Lwrap) / Hmin + 1.0) + 3.0) +
+           16.0 * u;
+}
+
+// FP64 decision r_ij^2 < T for sorted particles i and j: the same expression
+// as the FP64 path (minimum image per axis, no contraction).
+__device__ __forceinline__ bool exact_inside(const double *xs, const double *ys, const double *zs,
+                                             int64_t i, int64_t j, double T, bool per,
+                                             const SetGeom &g) {
+    double dx = xs[j] - xs[i], dy = ys[j] - ys[i], dz = zs[j] - zs[i];
+    if (per) {
+        dx = min_image(dx, g.L[0], g.halfL[0]);
+        dy = min_image(dy, g.L[1], g.halfL[1]);
+        dz = min_image(dz, g.L[2], g.halfL[2]);
+    }
+    return r2_exact(dx, dy, dz) < T;
+}
+
 // FP64 tiles: the minimum image is the identity for every pair of the tile
 // when each candidate lies within half a box minus the group's extent of the
 // group centre on every axis (|x_j - x_i| <= |x_j - gc| + |gc - x_i|), so such
@@ -734,14 +789,20 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
-    // candidates (x y z m); between tiles the same LDS holds the refinement stage
-    constexpr int kTileBytes = 4 * kWave * (int)sizeof(R);
+    // candidates (x y z m) and, in the mixed path, the candidates' sorted
+    // indices, per-sink counts of pairs the FP64 re-test rejected and the
+    // sinks' FP64 H (exact membership); between tiles the same LDS holds the
+    // refinement stage
+    constexpr int kTileBytes = 4 * kWave * (int)sizeof(R) + (MIXED ? kWave * 16 : 0);
     __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
                                                                                   : kRefineStageBytes];
     R *const tx = reinterpret_cast<R *>(tile_buf);
     R *const ty = tx + kWave;
     R *const tz = ty + kWave;
     R *const tm = tz + kWave;
+    int32_t *const tj = reinterpret_cast<int32_t *>(tm + kWave);
+    int32_t *const srej = tj + kWave;
+    double *const sH = reinterpret_cast<double *>(srej + kWave);
     float *const stage = reinterpret_cast<float *>(tile_buf);
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
     __shared__ double acc0[kWave], acc1[kWave], acc2[kWave];
@@ -755,7 +816,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int lb = 31 - __builtin_clz((unsigned)a.B);   // B = 2^lb
     const double slop = set_slop(g);
     const double cap = set_hcap(g, per, a.h_max);
-    const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
+    const int64_t i0 = g.p0 + (grp - g.g0) * kGroup;   // the group's first sink
+    const int64_t i = i0 + lane;
     const bool act = i < g.p1;
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double mi = act ? a.ms[i] : 0.0;
@@ -782,6 +844,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
     double gext[3];
     for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
+    const double gmax = fmax(gext[0], fmax(gext[1], gext[2]));
+    const double Lmax = fmax(g.L[0], fmax(g.L[1], g.L[2]));
     const R Lf[3] = {(R)g.L[0], (R)g.L[1], (R)g.L[2]};
     const R hLf[3] = {(R)g.halfL[0], (R)g.halfL[1], (R)g.halfL[2]};
     R qx, qy, qz;
@@ -803,6 +867,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     bool linear = false;
     int overflows = 0;
     int scans = 0, rewalks = 0;
+    int retests = 0;   // pairs the wave re-tested in FP64 (mixed)
     unsigned long long cand_tested = 0;
     bool need_walk = true;
 
@@ -830,7 +895,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         int cnt = 0;
         const R Hr = (R)H;
         const R Hinv = R(1) / Hr;
-        const R H2 = MIXED ? Hr * Hr : (R)(H * H);
+        // mixed: the FP32 test accepts r^2 < H^2 (1 + band), pairs with
+        // q >= 1 - band are re-tested in FP64 (see guard_band)
+        const double band =
+            MIXED ? guard_band(gmax, wave_min(act ? H : DBL_MAX), wrapf ? Lmax : 0.0) : 0.0;
+        const R H2 = MIXED ? (R)(H * H * (1.0 + band)) : (R)(H * H);
+        const R qlo = (R)(1.0 - band);
         sp[lane].w = Hinv;
         bool first_chunk = true;
         while (true) {
@@ -855,6 +925,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                           stage, ws);
             }
             const int ntile = sweep_tiles(ws.ncand, a.B);
+            if constexpr (MIXED) {
+                // (after the refinement, which shares this LDS)
+                sH[lane] = H;
+                srej[lane] = 0;
+            }
             for (int t = 0; t < ntile; ++t) {
                 int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
                                                : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
@@ -869,6 +944,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                             d2 = min_image(d2, g.L[2], g.halfL[2]);
                         }
                         tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2; tm[lane] = mj;
+                        tj[lane] = (int32_t)j;
                     } else {
                         tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j]; tm[lane] = mj;
                         far = needs_image(per, g, gc, gext, a.xs[j], a.ys[j], a.zs[j]);
@@ -900,11 +976,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                         return b;
                     }, [&](int s, int k) {
                         return PD{s, tx[k], ty[k], tz[k], tm[k], sp[s]};
-                    }, [&](const PD &d, bool valid) {
+                    }, [&](const PD &d, bool valid, bool decided) -> bool {
                         R ex, ey, ez;
                         const R r2 = pair_r2<MIXED, WRAP, R>(d.x, d.y, d.z, d.si.x, d.si.y,
                                                              d.si.z, per, g, Lf, hLf, ex, ey, ez);
                         const R q = pair_sqrt(r2) * d.si.w;
+                        // near the boundary the FP64 test decides (mixed, rare)
+                        if (MIXED && !decided && valid && q >= qlo) return true;
                         R f, t1, t2;
                         shape_f_t1_t2<K, R>(q, f, t1, t2);
                         if (valid) {
@@ -912,6 +990,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                             atomicAdd(&acc1[d.s], (double)(d.m * t1));
                             atomicAdd(&acc2[d.s], (double)(d.m * t2));
                         }
+                        return false;
+                    }, [&](int s_, int k_, bool act_) -> bool {
+                        bool in = false;
+                        if (act_) {
+                            const double Hs = sH[s_];
+                            in = exact_inside(a.xs, a.ys, a.zs, i0 + s_, (int64_t)tj[k_], Hs * Hs,
+                                              per, g);
+                            if (!in) atomicAdd(&srej[s_], 1);
+                        }
+                        retests += __popcll(__ballot(act_));
+                        return in;
                     }, cnt);
                 };
                 if (wrapf) tile(std::true_type{});
@@ -921,6 +1010,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 T1 += acc1[lane];
                 T2 += acc2[lane];
                 acc0[lane] = 0; acc1[lane] = 0; acc2[lane] = 0;
+                if constexpr (MIXED) {
+                    cnt -= srej[lane];
+                    srej[lane] = 0;
+                }
             }
             first_chunk = false;
             if (ws.nstack == 0) break;  // walk finished
@@ -988,6 +1081,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         if (scans >= a.maxit) break;
         if (__any(want_walk)) { need_walk = true; ++rewalks; }
     }
+    // status word: the iteration limit reached, a non-finite result
+    const bool iterlim = act && !done;
+    const bool nonfinite = act && !(isfinite(H) && isfinite(rho) && isfinite(om));
     if (act) {
         if (!done) noconv = true;
         a.Hs[i] = H;
@@ -998,7 +1094,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     int pairs_n = wave_sum_i(act ? cnt_out : 0);
     int bad = wave_sum_i((act && noconv) ? 1 : 0);
     int nact = wave_sum_i(act ? 1 : 0);
+    const int nlim = wave_sum_i(iterlim ? 1 : 0);
+    const int nnan = wave_sum_i(nonfinite ? 1 : 0);
+    const int nret = retests;   // (a wave total)
     if (lane == 0) {
+        if (nlim) atomicAdd(&a.cnt[C_ITERLIM], (unsigned long long)nlim);
+        if (nnan) atomicAdd(&a.cnt[C_NONFINITE], (unsigned long long)nnan);
+        if (nret) atomicAdd(&a.cnt[C_RETEST], (unsigned long long)nret);
         atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_PAIRS_D_TOT], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_CAND_D], cand_tested * (unsigned long long)nact);
@@ -1024,9 +1126,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
-    // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho)
-    // between tiles the same LDS holds the refinement stage
-    constexpr int kTileBytes = 5 * kWave * (int)sizeof(R) + 2 * kWave * (int)sizeof(V4<R>);
+    // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho), in the mixed
+    // path also their sorted indices (exact membership); between tiles the
+    // same LDS holds the refinement stage
+    constexpr int kTileBytes = 5 * kWave * (int)sizeof(R) + 2 * kWave * (int)sizeof(V4<R>) +
+                               (MIXED ? kWave * 4 : 0);
     __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
                                                                                   : kRefineStageBytes];
     V4<R> *const tv = reinterpret_cast<V4<R> *>(tile_buf);
@@ -1036,6 +1140,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     R *const tz = ty + kWave;
     R *const th2 = tz + kWave;
     R *const tm = th2 + kWave;
+    int32_t *const tj = reinterpret_cast<int32_t *>(tm + kWave);
     float *const stage = reinterpret_cast<float *>(tile_buf);
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink: (x H) (v 1/H) (A c rho sigma/H^5)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
@@ -1050,7 +1155,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     const bool per = a.periodic != 0;
     const int lb = 31 - __builtin_clz((unsigned)a.B);   // B = 2^lb
     const double slop = set_slop(g);
-    const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
+    const int64_t i0 = g.p0 + (grp - g.g0) * kGroup;   // the group's first sink
+    const int64_t i = i0 + lane;
     const bool act = i < g.p1;
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double Hd = act ? a.Hs[i] : 0.0;
@@ -1066,6 +1172,19 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     const R Lf[3] = {(R)g.L[0], (R)g.L[1], (R)g.L[2]};
     const R hLf[3] = {(R)g.halfL[0], (R)g.halfL[1], (R)g.halfL[2]};
     const double Hsink_max = wave_max(act ? Hd : 0.0);
+    // mixed: the FP32 test accepts r^2 < max(H_i, H_j)^2 (1 + band), pairs with
+    // r >= max(H_i, H_j) (1 - band) are re-tested in FP64 (see guard_band).
+    // A group that needs the re-wrapped differences gets the wider band.
+    double band = 0.0, bandw = 0.0;
+    if constexpr (MIXED) {
+        const double gmax = fmax(gext[0], fmax(gext[1], gext[2]));
+        const double Lmax = fmax(g.L[0], fmax(g.L[1], g.L[2]));
+        const double hmin = wave_min(act ? Hd : DBL_MAX);
+        band = guard_band(gmax, hmin, 0.0);
+        bandw = guard_band(gmax, hmin, Lmax);
+    }
+    const R band1 = (R)(1.0 + band), qlo = (R)(1.0 - band);
+    const R band1w = (R)(1.0 + bandw), qlow = (R)(1.0 - bandw);
 
     R qx, qy, qz;
     if constexpr (MIXED) {
@@ -1076,7 +1195,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
         qx = xi[0]; qy = xi[1]; qz = xi[2];
     }
     const R Hi = (R)Hd;
-    const R Hi2 = MIXED ? Hi * Hi : (R)(Hd * Hd);
+    const R Hi2 = MIXED ? (R)(Hd * Hd * (1.0 + band)) : (R)(Hd * Hd);
+    const R Hi2w = MIXED ? (R)(Hd * Hd * (1.0 + bandw)) : Hi2;
     const R Ai = (R)(act ? a.As[i] : 0.0);
     const R ci = (R)(act ? a.css[i] : 0.0);
     // sink data for the interaction phase
@@ -1097,6 +1217,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
 
     double acc_d[4] = {0, 0, 0, 0};
     int cnt = 0;
+    int rej = 0;       // accepted pairs that the FP64 re-test rejected (wave total)
+    int retests = 0;   // pairs the wave re-tested in FP64
     unsigned long long cand_tested = 0;
     walk_reset(stack, ws, linear, g);
 
@@ -1108,6 +1230,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
             linear = true;
             for (int q = 0; q < 4; ++q) acc_d[q] = 0;
             cnt = 0;
+            rej = 0;
+            retests = 0;
             cand_tested = 0;
             amu[lane] = 0;
             walk_reset(stack, ws, true, g);
@@ -1119,6 +1243,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
             int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
                                            : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
             bool far = false;
+            R hj = R(0);   // (mixed) the candidate's H, 0 for an empty slot
             if (j >= 0) {
                 if constexpr (MIXED) {
                     double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
@@ -1134,11 +1259,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                 }
                 if constexpr (MIXED) {
                     // FP32 records prepared once per particle by the EOS pass
+                    // (H^2 with the band is written below, once the tile's
+                    // wrap mode is known)
                     const V4<R> r1 = reinterpret_cast<const V4<R> *>(a.frec1)[j];
                     tv[lane] = r1;
                     tq[lane] = reinterpret_cast<const V4<R> *>(a.frec2)[j];
                     tm[lane] = a.fm[j];
-                    th2[lane] = r1.w * r1.w;
+                    hj = r1.w;
+                    tj[lane] = (int32_t)j;
                 } else {
                     const double Hj = a.Hs[j];
                     tm[lane] = (R)a.ms[j];
@@ -1157,8 +1285,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
             if constexpr (MIXED) {
                 // (H of the staged candidates, 0 for empty slots; the FP32 value is
                 // within the 1e-6 margin of the test)
-                double reach = fmax(Hsink_max, wave_max((double)tv[lane].w));
+                double reach = fmax(Hsink_max, wave_max((double)hj));
                 wrapf = group_needs_wrap(per, g, gext, reach);
+                th2[lane] = hj * hj * (wrapf ? band1w : band1);
             } else {
                 wrapf = __any(far);
             }
@@ -1172,7 +1301,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                     R dx, dy, dz;
                     const R r2 = pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
                                                          dx, dy, dz);
-                    return push_hit(b, r2, Hi2 > h2 ? Hi2 : h2);
+                    const R hi2 = WRAP ? Hi2w : Hi2;
+                    return push_hit(b, r2, hi2 > h2 ? hi2 : h2);
                 };
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
                 tile_pairs<1>(ring, [&](int k0, uint32_t b) {
@@ -1188,7 +1318,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                     return b;
                 }, [&](int s, int k) {
                     return PF{s, tx[k], ty[k], tz[k], tm[k], tv[k], tq[k], sp[s], sv[s], sq[s]};
-                }, [&](const PF &d, bool valid) {
+                }, [&](const PF &d, bool valid, bool decided) -> bool {
                     const int s = d.s;
                     const V4<R> &cv = d.cv, &cq = d.cq, &ip = d.ip, &iv = d.iv, &iq = d.iq;
                     R ex, ey, ez;
@@ -1196,6 +1326,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                                                          per, g, Lf, hLf, ex, ey, ez);
                     const R r = pair_sqrt(r2);
                     const R Hs_ = ip.w, Hj = cv.w;
+                    // near the boundary the FP64 test decides (mixed, rare)
+                    if (MIXED && !decided && valid &&
+                        r >= (Hs_ > Hj ? Hs_ : Hj) * (WRAP ? qlow : qlo))
+                        return true;
                     R Gi = 0, Gj = 0;
                     // (the sink's sigma / H^5 is prepared once, in its record)
                     if constexpr (K == 0) {
@@ -1237,6 +1371,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                         atomicAdd(&acc[3][s], (double)(mj * vdotx * (iq.x * Gi + R(0.5) * Pi * Gbar)));
                         if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
+                    return false;
+                }, [&](int s_, int k_, bool act_) -> bool {
+                    bool in = false;
+                    if (act_) {
+                        const int64_t jj = (int64_t)tj[k_];
+                        const double hi_ = a.Hs[i0 + s_], hj_ = a.Hs[jj];
+                        in = exact_inside(a.xs, a.ys, a.zs, i0 + s_, jj,
+                                          fmax(hi_ * hi_, hj_ * hj_), per, g);
+                    }
+                    retests += __popcll(__ballot(act_));
+                    rej += __popcll(__ballot(act_ && !in));
+                    return in;
                 }, cnt);
             };
             if (wrapf) tile(std::true_type{});
@@ -1252,6 +1398,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     }
     __syncthreads();
     const R mumax = bits_to_real(amu[lane]);
+    bool nonfinite = false;
     if (act) {
         const double axv = acc_d[0], ayv = acc_d[1], azv = acc_d[2];
         a.ax[i] = axv;
@@ -1259,16 +1406,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
         a.az[i] = azv;
         a.du[i] = acc_d[3];
         double amag = sqrt(axv * axv + ayv * ayv + azv * azv);
+        double den = (1.0 + 0.6 * a.alpha) * (double)ci + 0.6 * a.beta * (double)mumax;
         double dtv = a.dt_max;
         if (amag > 0.0) dtv = fmin(dtv, a.eta_a * sqrt(Hd / amag));
-        double den = (1.0 + 0.6 * a.alpha) * (double)ci + 0.6 * a.beta * (double)mumax;
         if (den > 0.0) dtv = fmin(dtv, a.eta_c * 0.5 * Hd / den);
+        // a non-finite |a| or signal speed gives no limit: the step is NaN
+        // (fmin would otherwise drop it) and the status word says so
+        if (!isfinite(amag) || !isfinite(den)) dtv = NAN;
         a.dt[i] = dtv;
+        nonfinite = !isfinite(dtv) || !isfinite(acc_d[3]);
     }
     // the particle itself passed the distance test once (r = 0)
-    int pairs_n = wave_sum_i(act ? cnt - 1 : 0);
+    int pairs_n = wave_sum_i(act ? cnt - 1 : 0) - rej;
     int nact = wave_sum_i(act ? 1 : 0);
+    const int nnan = wave_sum_i(nonfinite ? 1 : 0);
+    const int nret = retests;   // (a wave total)
     if (lane == 0) {
+        if (nnan) atomicAdd(&a.cnt[C_NONFINITE], (unsigned long long)nnan);
+        if (nret) atomicAdd(&a.cnt[C_RETEST], (unsigned long long)nret);
         atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_PAIRS_F_TOT], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_CAND_F], cand_tested * (unsigned long long)nact);
