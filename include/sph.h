@@ -237,6 +237,21 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
  * Timing is skipped inside graph capture. */
 sph_status sph_set_timing(sph_ctx *ctx, int32_t enable);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the start-up
+ * pass of sph_init (tree build, density with the smoothing-length iteration,
+ * forces) for one particle set of n <= 65536 particles, with no context and
+ * no device or pinned allocation.  Every work array is carved out of one
+ * static 32 MiB device array that each GPU the library runs on holds until
+ * the process ends.  Reads x y z vx vy vz m u H (H = first guess); writes H,
+ * rho, omega, P, c, ax ay az, dudt, dt, equal to what sph_init writes for
+ * the same parameters and particles.  Enqueued on `stream`; no counters or
+ * status word are kept.  All calls on one GPU share the static array: calls
+ * that overlap on one GPU (other streams, other threads) race.  Returns
+ * SPH_ERR_CAPACITY for n > 65536 and SPH_ERR_INVALID for bad parameters or
+ * NULL arrays, enqueueing nothing. */
+sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t n, void *stream);
+
 /* Synchronises the context's last stream and copies the counters and the
  * status word of the last call (which is then not reported again by the next
  * call).  Returns SPH_OK whenever the copy succeeds. */

@@ -32,7 +32,7 @@ MODE_GATHER, MODE_FORCE = 0, 1
 SYMBOLS = ("sph_default_params", "sph_version", "sph_last_error", "sph_create",
            "sph_create_batch", "sph_destroy", "sph_build_tree", "sph_neighbors", "sph_density",
            "sph_forces", "sph_init", "sph_step", "sph_graph_capture_step", "sph_graph_launch",
-           "sph_autotune", "sph_get_stats", "sph_set_timing")
+           "sph_autotune", "sph_get_stats", "sph_set_timing", "sph_init_noalloc")
 
 
 class Params(ctypes.Structure):
@@ -92,9 +92,10 @@ _lib.sph_graph_launch.argtypes = [_ctx_p, c_void_p]
 _lib.sph_autotune.argtypes = [_ctx_p, POINTER(Particles), POINTER(c_int32), c_void_p]
 _lib.sph_get_stats.argtypes = [_ctx_p, POINTER(Stats)]
 _lib.sph_set_timing.argtypes = [_ctx_p, c_int32]
+_lib.sph_init_noalloc.argtypes = [POINTER(Params), POINTER(Particles), c_int64, c_void_p]
 for _f in ("sph_create", "sph_create_batch", "sph_build_tree", "sph_neighbors", "sph_density",
            "sph_forces", "sph_init", "sph_step", "sph_graph_capture_step", "sph_graph_launch",
-           "sph_autotune", "sph_get_stats", "sph_set_timing"):
+           "sph_autotune", "sph_get_stats", "sph_set_timing", "sph_init_noalloc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -106,6 +107,15 @@ class SphError(RuntimeError):
 
 def version() -> str:
     return _lib.sph_version().decode()
+
+
+def init_noalloc(params: dict, P: "ParticleArrays", stream=None) -> None:
+    """sph_init_noalloc: the start-up pass without a context or any allocation
+    (n <= 65536; work arrays in the library's static device array)."""
+    q = make_params(params)
+    st = _lib.sph_init_noalloc(ctypes.byref(q), ctypes.byref(P.c), P.n, _stream_ptr(stream))
+    if st != SPH_OK:
+        raise SphError(st, "sph_init_noalloc failed")
 
 
 def make_params(p: dict) -> Params:

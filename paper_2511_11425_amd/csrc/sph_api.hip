@@ -391,6 +391,57 @@ sph_status do_step(sph_ctx *x, sph_particles *p, double dt, hipStream_t s) {
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free start-up
+//
+// sph_init_noalloc runs the start-up pass of sph_init (tree build, density,
+// forces) with every work array carved out of one file-scope device array,
+// `scratch`, instead of device allocations: for callers that cannot
+// allocate.  Each GPU the library runs on holds its own copy of the array
+// (kNoAllocBytes) until the process ends; the host keeps its device address,
+// obtained once per device with hipGetSymbolAddress, and passes that address
+// (never the array's host-side name) to every launch.  All calls on one GPU
+// share the array, which keeps the last call's contents: everything a call
+// reads is written or cleared by that call first, and calls that overlap on
+// one GPU race.
+constexpr int64_t kNoAllocMaxN = 65536;          // particles per call
+constexpr size_t kNoAllocBytes = 32ull << 20;    // 32 MiB per GPU
+constexpr int kNoAllocDevices = 16;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+unsigned char *g_scratch[kNoAllocDevices] = {};   // device address of `scratch` per GPU
+sph_ctx g_noalloc[kNoAllocDevices];               // host state per GPU (no allocation)
+
+// Bump allocator over the scratch array (256-byte aligned pieces).
+struct Carve {
+    unsigned char *base;
+    size_t off, cap;
+    bool ok;
+    template <typename T> void take(T **p, size_t count) {
+        const size_t bytes = (sizeof(T) * (count > 0 ? count : 1) + 255) & ~(size_t)255;
+        if (!ok || off + bytes > cap) { ok = false; *p = nullptr; return; }
+        *p = reinterpret_cast<T *>(base + off);
+        off += bytes;
+    }
+};
+
+// Topology of one set written on the device (no host-to-device copies).
+__global__ void k_one_set_topology(SetGeom *sets, int32_t *grp_set, int64_t ng, int32_t *bkt_set,
+                                   int64_t nb, int64_t *pref, int max_depth, SetGeom g) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) sets[0] = g;
+    if (t < ng) grp_set[t] = 0;
+    if (t < nb) bkt_set[t] = 0;
+    if (t <= max_depth) {
+        pref[2 * t] = 0;
+        pref[2 * t + 1] = g.nb > 0 ? (int64_t)(g.nbp >> t) : 0;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -750,6 +801,100 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     if (st != SPH_OK) return st;
     *bucket = best;
     return SPH_OK;
+}
+
+sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t n, void *stream) {
+    std::string why;
+    if (!valid_params(params, why)) return SPH_ERR_INVALID;
+    if (n < 0) return SPH_ERR_INVALID;
+    if (n > kNoAllocMaxN) return SPH_ERR_CAPACITY;   // beyond the static work space
+    if (check_particles(nullptr, p, true, n) != SPH_OK) return SPH_ERR_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPH_ERR_HIP;
+    if (dev < 0 || dev >= kNoAllocDevices) return SPH_ERR_INVALID;
+    if (!g_scratch[dev]) {
+        // once per GPU, with that GPU current: the device address of its copy
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPH_ERR_HIP;
+        g_scratch[dev] = static_cast<unsigned char *>(ptr);
+        g_noalloc[dev].c.level_total.reserve(64);   // host bookkeeping, sized once
+    }
+    sph_ctx *const x = &g_noalloc[dev];
+    Ctx &c = x->c;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    c.prm = *params;
+    if (!(c.prm.nr_tol > 0)) c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-5 : 1e-14;
+    if (c.prm.stack_limit == 0) c.prm.stack_limit = kStackCap;
+    c.bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    c.nsets = 1;
+    c.timing = false;
+    c.capturing = false;
+    c.last_stream = s;
+    if (n == 0) return SPH_OK;
+
+    // topology of one set of n particles
+    const int B = c.bucket;
+    SetGeom g{};
+    g.p0 = 0;
+    g.p1 = n;
+    const int64_t nb = (n + B - 1) / B;
+    int64_t nbp = 1;
+    int depth = 0;
+    while (nbp < nb) { nbp <<= 1; ++depth; }
+    g.nb = (int32_t)nb;
+    g.nbp = (int32_t)nbp;
+    g.depth = depth;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = c.prm.box_lo[a];
+        g.L[a] = c.prm.box_hi[a] - c.prm.box_lo[a];
+        g.halfL[a] = 0.5 * g.L[a];
+    }
+    c.n = n;
+    c.nbuckets = nb;
+    c.ngroups = (n + kGroup - 1) / kGroup;
+    c.nnodes = 2 * nbp;
+    c.max_depth = depth;
+    c.level_total.assign(depth + 1, 0);   // within the reserved capacity
+    for (int d = 0; d <= depth; ++d) c.level_total[d] = nbp >> d;
+    c.set_bits = 0;
+    c.key_passes = (3 * key_bits_per_axis() + 7) / 8;
+    c.sort_blocks = sort_blocks_needed(n);
+    c.scan_tmp_len = scan_tmp_needed(std::max<int64_t>(n + 1, 256 * std::max<int64_t>(c.sort_blocks, 1)));
+
+    Carve cv{g_scratch[dev], 0, kNoAllocBytes, true};
+    int64_t *pref = nullptr;
+    cv.take(&c.d_sets, 1);
+    cv.take(&c.d_grp_set, c.ngroups);
+    cv.take(&c.d_bkt_set, nb);
+    cv.take(&pref, 2 * (depth + 1));
+    c.d_level_pref = pref;
+    cv.take(&c.d_key[0], n); cv.take(&c.d_key[1], n);
+    cv.take(&c.d_perm[0], n); cv.take(&c.d_perm[1], n);
+    cv.take(&c.d_hist, 2 * 256 * std::max<int64_t>(c.sort_blocks, 1));
+    cv.take(&c.d_bbox, 6);
+    cv.take(&c.xs, n); cv.take(&c.ys, n); cv.take(&c.zs, n); cv.take(&c.ms, n); cv.take(&c.Hs, n);
+    cv.take(&c.vxs, n); cv.take(&c.vys, n); cv.take(&c.vzs, n); cv.take(&c.us, n);
+    cv.take(&c.rhos, n); cv.take(&c.oms, n); cv.take(&c.As, n); cv.take(&c.css, n); cv.take(&c.Ps, n);
+    if (c.prm.precision == SPH_PREC_MIXED) {
+        cv.take(&c.frec1, 4 * n); cv.take(&c.frec2, 4 * n); cv.take(&c.fm, n);
+    }
+    cv.take(&c.axs, n); cv.take(&c.ays, n); cv.take(&c.azs, n); cv.take(&c.dus, n); cv.take(&c.dts, n);
+    cv.take(&c.nodes, c.nnodes);
+    cv.take(&c.d_wstack, (size_t)c.ngroups * kStackCap);
+    cv.take(&c.d_scan_tmp, c.scan_tmp_len);
+    cv.take(&c.d_cnt, C_NCOUNTERS);
+    if (!cv.ok) return SPH_ERR_CAPACITY;
+
+    const int64_t nt = std::max<int64_t>(std::max<int64_t>(c.ngroups, nb), depth + 1);
+    k_one_set_topology<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(
+        c.d_sets, c.d_grp_set, c.ngroups, c.d_bkt_set, nb, pref, depth, g);
+    if (hipGetLastError() != hipSuccess) return SPH_ERR_HIP;
+    if (launch_init_nodes(&c, s) != hipSuccess) return SPH_ERR_HIP;
+    if (launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s) != hipSuccess) return SPH_ERR_HIP;
+    if (launch_tree_build(&c, p, s) != hipSuccess) return SPH_ERR_HIP;
+    sph_status st = do_density(x, p, s);
+    if (st != SPH_OK) return st;
+    return do_forces(x, p, p->vx, p->vy, p->vz, p->u, false, s);
 }
 
 }  // extern "C"
