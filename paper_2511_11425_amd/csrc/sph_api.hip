@@ -56,6 +56,8 @@ void free_all(Ctx &c) {
     if (c.graph) { (void)hipGraphDestroy(c.graph); c.graph = nullptr; }
     for (void *q : c.allocs) (void)hipFree(q);
     c.allocs.clear();
+    c.frec1 = c.frec2 = c.fm = nullptr;
+    c.drec1 = c.drec2 = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
     if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
     if (c.h_flags) { (void)hipHostFree(c.h_flags); c.h_flags = nullptr; }
@@ -232,6 +234,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.vxs, n); A(c.vys, n); A(c.vzs, n); A(c.us, n);
     A(c.rhos, n); A(c.oms, n); A(c.As, n); A(c.css, n); A(c.Ps, n);
     if (c.prm.precision == SPH_PREC_MIXED) { A(c.frec1, 4 * n); A(c.frec2, 4 * n); A(c.fm, n); }
+    else { A(c.drec1, 4 * n); A(c.drec2, 4 * n); }
     A(c.axs, n); A(c.ays, n); A(c.azs, n); A(c.dus, n); A(c.dts, n);
     A(c.nodes, cap_nodes);
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
@@ -875,8 +878,12 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     cv.take(&c.xs, n); cv.take(&c.ys, n); cv.take(&c.zs, n); cv.take(&c.ms, n); cv.take(&c.Hs, n);
     cv.take(&c.vxs, n); cv.take(&c.vys, n); cv.take(&c.vzs, n); cv.take(&c.us, n);
     cv.take(&c.rhos, n); cv.take(&c.oms, n); cv.take(&c.As, n); cv.take(&c.css, n); cv.take(&c.Ps, n);
+    c.frec1 = c.frec2 = c.fm = nullptr;
+    c.drec1 = c.drec2 = nullptr;
     if (c.prm.precision == SPH_PREC_MIXED) {
         cv.take(&c.frec1, 4 * n); cv.take(&c.frec2, 4 * n); cv.take(&c.fm, n);
+    } else {
+        cv.take(&c.drec1, 4 * n); cv.take(&c.drec2, 4 * n);
     }
     cv.take(&c.axs, n); cv.take(&c.ays, n); cv.take(&c.azs, n); cv.take(&c.dus, n); cv.take(&c.dts, n);
     cv.take(&c.nodes, c.nnodes);

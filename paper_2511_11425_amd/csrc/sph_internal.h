@@ -105,6 +105,8 @@ struct Ctx {
     // mixed path: FP32 force-pass records of every particle, written by the EOS
     // pass in sorted order: (vx vy vz H), (1/H A c rho), m
     float *frec1 = nullptr, *frec2 = nullptr, *fm = nullptr;
+    // FP64 path: the same records in FP64, (vx vy vz H), (1/H A c rho)
+    double *drec1 = nullptr, *drec2 = nullptr;
     double *axs = nullptr, *ays = nullptr, *azs = nullptr, *dus = nullptr, *dts = nullptr;
     // FP32 bucket-relative offsets for the mixed path
 

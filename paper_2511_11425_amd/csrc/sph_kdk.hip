@@ -53,7 +53,8 @@ __global__ void k_scatter_cols(const uint32_t *__restrict__ perm, int64_t n, Col
 // the caller's arrays.
 struct ForceRecords {   // mixed path only (rec1 == nullptr otherwise)
     const double *m, *H, *vx, *vy, *vz;
-    float *rec1, *rec2, *fm;
+    float *rec1, *rec2, *fm;     // mixed path
+    double *drec1, *drec2;       // FP64 path
 };
 
 __global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, double gam, double P0,
@@ -84,6 +85,13 @@ __global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, dou
         r1[k] = make_float4((float)fr.vx[k], (float)fr.vy[k], (float)fr.vz[k], (float)H);
         r2[k] = make_float4((float)(1.0 / H), (float)A, (float)c, (float)r);
         fr.fm[k] = (float)fr.m[k];
+    }
+    if (fr.drec1) {
+        const double H = fr.H[k];
+        double4 *r1 = reinterpret_cast<double4 *>(fr.drec1);
+        double4 *r2 = reinterpret_cast<double4 *>(fr.drec2);
+        r1[k] = make_double4(fr.vx[k], fr.vy[k], fr.vz[k], H);
+        r2[k] = make_double4(1.0 / H, A, c, r);
     }
     uint32_t i = perm[k];
     Pc[i] = P;
@@ -301,7 +309,8 @@ hipError_t launch_scatter(Ctx *c, const Cols &cols, hipStream_t s) {
 hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *c_caller,
                       hipStream_t s) {
     if (c->n == 0) return hipSuccess;
-    ForceRecords fr{c->ms, c->Hs, c->vxs, c->vys, c->vzs, c->frec1, c->frec2, c->fm};
+    ForceRecords fr{c->ms, c->Hs, c->vxs, c->vys, c->vzs, c->frec1, c->frec2, c->fm,
+                    c->drec1, c->drec2};
     k_eos<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->n, c->prm.eos, c->prm.gamma,
                                                     c->prm.P0, c->rhos, u_sorted, c->oms, c->Ps,
                                                     c->css, c->As, P_caller, c_caller, fr);

@@ -512,6 +512,7 @@ struct SweepArgs {
     double *Hs, *rhos, *oms;
     const double *vxs, *vys, *vzs, *As, *css;
     const float *frec1, *frec2, *fm;   // mixed force records (see the EOS pass)
+    const double *drec1, *drec2;       // FP64 force records
     double *ax, *ay, *az, *du, *dt;
     unsigned long long *cnt;
     int B;
@@ -606,6 +607,11 @@ __device__ __forceinline__ int64_t sweep_slot(const SetGeom &g, const uint32_t *
 // need only a compiler-level ordering point (a workgroup barrier would also
 // wait for every outstanding LDS atomic).
 constexpr int kRing = 128;
+
+// Candidate queue of the sweeps: a ring of two tiles.  A load of 64 slots
+// appends at most 64 candidates to fewer than 64 queued ones, and every time
+// 64 are queued the half they start in is processed as a tile.
+constexpr int kQueue = 2 * kWave;
 
 // Hit bits are collected most significant first: `push_hit(acc, a, b)` is
 // 2 acc + (a < b), one compare whose lane mask is the carry-in of one add, in
@@ -764,6 +770,92 @@ __device__ __forceinline__ bool exact_inside(const double *xs, const double *ys,
     return r2_exact(dx, dy, dz) < T;
 }
 
+// One candidate slot of the fill loop: sorted index (-1: empty) and FP64
+// position plus one more column (m for the density pass, H for the force pass).
+struct Slot {
+    int64_t j;
+    double x, y, z, w;
+};
+
+// ================================================================ candidate filter
+//
+// The walk and the refinement keep whole buckets; within a kept bucket most
+// particles are still out of reach of every sink.  Before a candidate enters
+// the queue that the distance tests read, it is tested once (one lane per
+// candidate, not per pair) against bounds of the whole group, relative to
+// the group centre gc: the box of the sinks' kernel balls and a ball around
+// gc that encloses them (the gather test of Sec. 2.3.2 applied to a single
+// particle), or, in the force pass, also whether the candidate's own ball
+// reaches the box of the sink positions (the scatter test).  The bounds are
+// widened by 1e-5 of the group's reach, far beyond the rounding of either
+// precision and the mixed path's membership band, so the filter drops only
+// candidates that no sink can accept.  A candidate whose offset from gc comes
+// within the group's extent of half a box may need another periodic image
+// for some sink; it is kept untested.
+struct GroupFilter {
+    float blo[3], bhi[3];   // box of the sinks' balls
+    float clo[3], chi[3];   // box of the sink positions
+    float R2;               // squared radius of the ball around gc holding every sink ball
+    float lim[3];           // per axis: offsets beyond this may need another image
+    float eps;              // absolute widening
+    bool per;
+
+    __device__ __forceinline__ bool ambiguous(float d0, float d1, float d2) const {
+        return per && (fabsf(d0) >= lim[0] || fabsf(d1) >= lim[1] || fabsf(d2) >= lim[2]);
+    }
+    // gather: some sink's ball may hold the candidate
+    __device__ __forceinline__ bool gather(float d0, float d1, float d2) const {
+        return d0 >= blo[0] && d0 <= bhi[0] && d1 >= blo[1] && d1 <= bhi[1] && d2 >= blo[2] &&
+               d2 <= bhi[2] && fmaf(d0, d0, fmaf(d1, d1, d2 * d2)) <= R2;
+    }
+    __device__ __forceinline__ bool inside(float d0, float d1, float d2) const {
+        return ambiguous(d0, d1, d2) || gather(d0, d1, d2);
+    }
+    // force set: gather, or the candidate's ball of radius Hj reaches a sink
+    __device__ __forceinline__ bool inside_fs(float d0, float d1, float d2, float Hj) const {
+        const float e0 = fmaxf(fmaxf(clo[0] - d0, d0 - chi[0]), 0.0f);
+        const float e1 = fmaxf(fmaxf(clo[1] - d1, d1 - chi[1]), 0.0f);
+        const float e2 = fmaxf(fmaxf(clo[2] - d2, d2 - chi[2]), 0.0f);
+        const float rj = fmaf(Hj, 1.0f + 1e-5f, eps);
+        return ambiguous(d0, d1, d2) || gather(d0, d1, d2) ||
+               fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) <= rj * rj;
+    }
+};
+
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// The filter of a group whose sinks (lanes with `act`) sit at xi with support
+// radius H.  Bounds are reduced in FP64 and rounded to FP32 with their
+// widening (1e-5 of the reach, against FP32's 6e-8), the candidate offsets
+// they are compared with are the FP32 roundings of the FP64 ones.
+__device__ inline GroupFilter group_filter(bool act, const double *xi, const double *gc, double H,
+                                           bool per, const SetGeom &g, const double *gext) {
+    GroupFilter f;
+    f.per = per;
+    double q[3];
+    for (int c = 0; c < 3; ++c) {
+        const double d = xi[c] - gc[c];
+        q[c] = act ? (per ? min_image(d, g.L[c], g.halfL[c]) : d) : 0.0;
+    }
+    const double Hmax = wave_max(act ? H : 0.0);
+    const double gm = fmax(gext[0], fmax(gext[1], gext[2]));
+    const double eps = 1e-5 * (gm + Hmax);
+    f.eps = uniform_f((float)eps);
+    const double Hw = H * (1.0 + 1e-5);
+    for (int c = 0; c < 3; ++c) {
+        f.blo[c] = uniform_f((float)(wave_min(act ? q[c] - Hw : DBL_MAX) - eps));
+        f.bhi[c] = uniform_f((float)(wave_max(act ? q[c] + Hw : -DBL_MAX) + eps));
+        f.clo[c] = uniform_f((float)(wave_min(act ? q[c] : DBL_MAX) - eps));
+        f.chi[c] = uniform_f((float)(wave_max(act ? q[c] : -DBL_MAX) + eps));
+        f.lim[c] = uniform_f((float)(0.499 * g.L[c] - gext[c]));
+    }
+    const double R = wave_max(act ? sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) + Hw : 0.0) + eps;
+    f.R2 = uniform_f((float)(R * R));
+    return f;
+}
+
 // FP64 tiles: the minimum image is the identity for every pair of the tile
 // when each candidate lies within half a box minus the group's extent of the
 // group centre on every axis (|x_j - x_i| <= |x_j - gc| + |gc - x_i|), so such
@@ -789,19 +881,20 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
-    // candidates (x y z m) and, in the mixed path, the candidates' sorted
-    // indices, per-sink counts of pairs the FP64 re-test rejected and the
-    // sinks' FP64 H (exact membership); between tiles the same LDS holds the
-    // refinement stage
-    constexpr int kTileBytes = 4 * kWave * (int)sizeof(R) + (MIXED ? kWave * 16 : 0);
+    // candidate queue (x y z m, a ring of kQueue entries; tiles are its
+    // halves) and, in the mixed path, the candidates' sorted indices,
+    // per-sink counts of pairs the FP64 re-test rejected and the sinks' FP64
+    // H (exact membership); while the walk refines its list the same LDS
+    // holds the refinement stage
+    constexpr int kTileBytes = 4 * kQueue * (int)sizeof(R) + (MIXED ? kQueue * 4 + kWave * 12 : 0);
     __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
                                                                                   : kRefineStageBytes];
-    R *const tx = reinterpret_cast<R *>(tile_buf);
-    R *const ty = tx + kWave;
-    R *const tz = ty + kWave;
-    R *const tm = tz + kWave;
-    int32_t *const tj = reinterpret_cast<int32_t *>(tm + kWave);
-    int32_t *const srej = tj + kWave;
+    R *const qx_ = reinterpret_cast<R *>(tile_buf);
+    R *const qy_ = qx_ + kQueue;
+    R *const qz_ = qy_ + kQueue;
+    R *const qm_ = qz_ + kQueue;
+    int32_t *const qj_ = reinterpret_cast<int32_t *>(qm_ + kQueue);
+    int32_t *const srej = qj_ + kQueue;
     double *const sH = reinterpret_cast<double *>(srej + kWave);
     float *const stage = reinterpret_cast<float *>(tile_buf);
     __shared__ V4<R> sp[kWave];   // sink: position, 1/H
@@ -902,6 +995,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         const R H2 = MIXED ? (R)(H * H * (1.0 + band)) : (R)(H * H);
         const R qlo = (R)(1.0 - band);
         sp[lane].w = Hinv;
+        // the group's bounds at this scan's H (candidate filter)
+        const GroupFilter fil = group_filter(act, xi, gc, H, per, g, gext);
+        int qb = 0, qn = 0;   // candidate queue: first entry, entries
         bool first_chunk = true;
         while (true) {
             if (!first_chunk || !list_complete) {
@@ -924,36 +1020,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 refine<false>(g, per, slop, a.nodes, xi, Hw, wave_max(act ? Hw : 0.0), act, gc, gext, cand,
                           stage, ws);
             }
-            const int ntile = sweep_tiles(ws.ncand, a.B);
+            const int nload = sweep_tiles(ws.ncand, a.B);
             if constexpr (MIXED) {
                 // (after the refinement, which shares this LDS)
                 sH[lane] = H;
                 srej[lane] = 0;
             }
-            for (int t = 0; t < ntile; ++t) {
-                int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
-                                               : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
-                bool far = false;
-                if (j >= 0) {
-                    const R mj = (R)a.ms[j];
-                    if constexpr (MIXED) {
-                        double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
-                        if (per) {
-                            d0 = min_image(d0, g.L[0], g.halfL[0]);
-                            d1 = min_image(d1, g.L[1], g.halfL[1]);
-                            d2 = min_image(d2, g.L[2], g.halfL[2]);
-                        }
-                        tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2; tm[lane] = mj;
-                        tj[lane] = (int32_t)j;
-                    } else {
-                        tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j]; tm[lane] = mj;
-                        far = needs_image(per, g, gc, gext, a.xs[j], a.ys[j], a.zs[j]);
-                    }
-                } else {
+            // One tile: the 64 queue entries from qb (nv of them valid).
+            auto run_tile = [&](int nv) {
+                R *const tx = qx_ + qb, *const ty = qy_ + qb, *const tz = qz_ + qb,
+                         *const tm = qm_ + qb;
+                const int32_t *const tj = qj_ + qb;
+                if (lane >= nv) {
                     tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
                 }
-                if constexpr (!MIXED) wrapf = __any(far);
-                cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
+                if constexpr (!MIXED)
+                    wrapf = __any(lane < nv && needs_image(per, g, gc, gext, (double)tx[lane],
+                                                           (double)ty[lane], (double)tz[lane]));
+                cand_tested += (unsigned long long)nv;
                 __syncthreads();
                 auto tile = [&](auto wrap_tag) {
                     constexpr bool WRAP = decltype(wrap_tag)::value;
@@ -1014,6 +1098,58 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                     cnt -= srej[lane];
                     srej[lane] = 0;
                 }
+            };
+            // Candidates are loaded 64 slots at a time; those the group's
+            // bounds at this scan's H rule out for every sink are dropped, the
+            // rest appended to the queue, and each full half of it is a tile.
+            // (one call site of the tile code: the loop flushes the last
+            // partial tile itself, before the walk refines again, whose stage
+            // shares this LDS, or the scan ends)
+            // (fetching the next slot during this one's filter, as the force
+            // pass does, costs the density kernel more in spilled registers
+            // at five waves per SIMD than it hides: 2.16 -> 2.32 ms at 2M)
+            for (int t = 0;;) {
+              if (t < nload) {
+                const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
+                                                     : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+                const Slot cur = j >= 0 ? Slot{j, a.xs[j], a.ys[j], a.zs[j], a.ms[j]}
+                                        : Slot{-1, 0.0, 0.0, 0.0, 0.0};
+                ++t;
+                R px = R(0), py = R(0), pz = R(0), pm = R(0);
+                bool keep = false;
+                if (j >= 0) {
+                    double d0 = cur.x - gc[0], d1 = cur.y - gc[1], d2 = cur.z - gc[2];
+                    if (per) {
+                        d0 = min_image(d0, g.L[0], g.halfL[0]);
+                        d1 = min_image(d1, g.L[1], g.halfL[1]);
+                        d2 = min_image(d2, g.L[2], g.halfL[2]);
+                    }
+                    keep = fil.inside((float)d0, (float)d1, (float)d2);
+                    pm = (R)cur.w;
+                    if constexpr (MIXED) {
+                        px = (R)d0; py = (R)d1; pz = (R)d2;
+                    } else {
+                        px = cur.x; py = cur.y; pz = cur.z;
+                    }
+                }
+                const uint64_t kb = __ballot(keep);
+                if (keep) {
+                    const int at = (qb + qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                   (uint32_t)(kb >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u))) &
+                                   (kQueue - 1);
+                    qx_[at] = px; qy_[at] = py; qz_[at] = pz; qm_[at] = pm;
+                    if constexpr (MIXED) qj_[at] = (int32_t)j;
+                }
+                qn += __popcll(kb);
+              }
+              if (qn >= kWave || (t >= nload && qn > 0)) {
+                const int nv = qn < kWave ? qn : kWave;
+                run_tile(nv);
+                qb ^= kWave;
+                qn -= nv;
+              }
+              if (t >= nload && qn == 0) break;
             }
             first_chunk = false;
             if (ws.nstack == 0) break;  // walk finished
@@ -1115,33 +1251,40 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // ================================================================ forces
 
 // Occupancy of the force kernels.  Their walk stack lives in global memory
-// (one per sink group, in L2 while the group runs), not in LDS: the 3 KiB it
-// frees bring the mixed kernel's LDS to 10 KiB, which admits four waves per
-// SIMD, and the mixed kernel is held to 128 VGPRs for them (the values that
-// spill to scratch cost less than the latency the fourth wave hides:
-// measured 4.21 -> 3.60 ms at 2M); the FP64 kernel's 16.5 KiB admit nine
-// waves per CU.
+// (one per sink group, in L2 while the group runs).  Both run three waves per
+// SIMD with up to 168 VGPRs: once the candidate filter had halved the
+// distance tests, the fourth wave of the mixed kernel (128 VGPRs, 52 of its
+// values spilled to scratch) cost more than it hid (2M mixed forces 3.81 ms
+// at four waves, 3.24 at three).
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4 : 3))) void k_forces(SweepArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
-    // candidates: x y z H^2 m (arrays) and (v H) (1/H A c rho), in the mixed
-    // path also their sorted indices (exact membership); between tiles the
-    // same LDS holds the refinement stage
-    constexpr int kTileBytes = 5 * kWave * (int)sizeof(R) + 2 * kWave * (int)sizeof(V4<R>) +
-                               (MIXED ? kWave * 4 : 0);
+    // candidate queue (a ring of kQueue entries; tiles are its halves): what
+    // the distance test reads, x y z and H^2, and the sorted index through
+    // which the interaction reads the candidate's force record (m, v, H, 1/H,
+    // A, c, rho; written once per particle by the EOS pass, and shared by the
+    // tile's pairs in the L1 cache); while the walk refines its list the same
+    // LDS holds the refinement stage
+    constexpr int kTileBytes = 4 * kQueue * (int)sizeof(R) + kQueue * 4;
     __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
                                                                                   : kRefineStageBytes];
-    V4<R> *const tv = reinterpret_cast<V4<R> *>(tile_buf);
-    V4<R> *const tq = tv + kWave;
-    R *const tx = reinterpret_cast<R *>(tq + kWave);
-    R *const ty = tx + kWave;
-    R *const tz = ty + kWave;
-    R *const th2 = tz + kWave;
-    R *const tm = th2 + kWave;
-    int32_t *const tj = reinterpret_cast<int32_t *>(tm + kWave);
+    R *const qx_ = reinterpret_cast<R *>(tile_buf);
+    R *const qy_ = qx_ + kQueue;
+    R *const qz_ = qy_ + kQueue;
+    R *const qh2_ = qz_ + kQueue;
+    int32_t *const qj_ = reinterpret_cast<int32_t *>(qh2_ + kQueue);
     float *const stage = reinterpret_cast<float *>(tile_buf);
+    const V4<R> *const rec1 = reinterpret_cast<const V4<R> *>(MIXED ? (const void *)a.frec1
+                                                                     : (const void *)a.drec1);
+    const V4<R> *const rec2 = reinterpret_cast<const V4<R> *>(MIXED ? (const void *)a.frec2
+                                                                     : (const void *)a.drec2);
+    // mixed: the tile's force records are staged in LDS (one round trip per
+    // tile instead of one per chunk of pairs); the FP64 kernel, whose LDS
+    // already limits its occupancy, reads them per pair through the L1 cache
+    __shared__ V4<R> trec1[MIXED ? kWave : 1], trec2[MIXED ? kWave : 1];
+    __shared__ R trm[MIXED ? kWave : 1];
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink: (x H) (v 1/H) (A c rho sigma/H^5)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
     __shared__ double acc[4][kWave];   // a_x a_y a_z du/dt
@@ -1197,6 +1340,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
     const R Hi = (R)Hd;
     const R Hi2 = MIXED ? (R)(Hd * Hd * (1.0 + band)) : (R)(Hd * Hd);
     const R Hi2w = MIXED ? (R)(Hd * Hd * (1.0 + bandw)) : Hi2;
+    const R wfac = (R)((1.0 + bandw) / (1.0 + band));   // staged H^2 of a wrapped tile
+    const GroupFilter fil = group_filter(act, xi, gc, Hd, per, g, gext);
     const R Ai = (R)(act ? a.As[i] : 0.0);
     const R ci = (R)(act ? a.css[i] : 0.0);
     // sink data for the interaction phase
@@ -1238,70 +1383,47 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
             continue;
         }
         refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
-        const int ntile = sweep_tiles(ws.ncand, a.B);
-        for (int t = 0; t < ntile; ++t) {
-            int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, ntile, lb)
-                                           : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
-            bool far = false;
-            R hj = R(0);   // (mixed) the candidate's H, 0 for an empty slot
-            if (j >= 0) {
-                if constexpr (MIXED) {
-                    double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
-                    if (per) {
-                        d0 = min_image(d0, g.L[0], g.halfL[0]);
-                        d1 = min_image(d1, g.L[1], g.halfL[1]);
-                        d2 = min_image(d2, g.L[2], g.halfL[2]);
-                    }
-                    tx[lane] = (R)d0; ty[lane] = (R)d1; tz[lane] = (R)d2;
-                } else {
-                    tx[lane] = a.xs[j]; ty[lane] = a.ys[j]; tz[lane] = a.zs[j];
-                    far = needs_image(per, g, gc, gext, a.xs[j], a.ys[j], a.zs[j]);
-                }
-                if constexpr (MIXED) {
-                    // FP32 records prepared once per particle by the EOS pass
-                    // (H^2 with the band is written below, once the tile's
-                    // wrap mode is known)
-                    const V4<R> r1 = reinterpret_cast<const V4<R> *>(a.frec1)[j];
-                    tv[lane] = r1;
-                    tq[lane] = reinterpret_cast<const V4<R> *>(a.frec2)[j];
-                    tm[lane] = a.fm[j];
-                    hj = r1.w;
-                    tj[lane] = (int32_t)j;
-                } else {
-                    const double Hj = a.Hs[j];
-                    tm[lane] = (R)a.ms[j];
-                    th2[lane] = (R)(Hj * Hj);
-                    tv[lane] = V4<R>{(R)a.vxs[j], (R)a.vys[j], (R)a.vzs[j], (R)Hj};
-                    tq[lane] = V4<R>{(R)(1.0 / Hj), (R)a.As[j], (R)a.css[j], (R)a.rhos[j]};
-                }
-            } else {
-                tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
-                th2[lane] = R(0);
-                tv[lane] = V4<R>{R(0), R(0), R(0), R(0)};
-                tq[lane] = V4<R>{R(0), R(0), R(0), R(1)};
+        const int nload = sweep_tiles(ws.ncand, a.B);
+        int qb = 0, qn = 0;   // candidate queue: first entry, entries
+        // One tile: the 64 queue entries from qb (nv of them valid).
+        auto run_tile = [&](int nv) {
+            R *const tx = qx_ + qb, *const ty = qy_ + qb, *const tz = qz_ + qb;
+            R *const th2 = qh2_ + qb;
+            const int32_t *const tj = qj_ + qb;
+            if (lane >= nv) {
+                tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); th2[lane] = R(0);
             }
-            cand_tested += (unsigned long long)__popcll(__ballot(j >= 0));
             bool wrapf = false;
             if constexpr (MIXED) {
-                // (H of the staged candidates, 0 for empty slots; the FP32 value is
-                // within the 1e-6 margin of the test)
-                double reach = fmax(Hsink_max, wave_max((double)hj));
+                // (the staged H^2 carry the band's 1 + band, within the 1e-6 margin)
+                const double reach =
+                    fmax(Hsink_max, sqrt(wave_max(lane < nv ? (double)th2[lane] : 0.0)));
                 wrapf = group_needs_wrap(per, g, gext, reach);
-                th2[lane] = hj * hj * (wrapf ? band1w : band1);
             } else {
-                wrapf = __any(far);
+                wrapf = __any(lane < nv &&
+                              needs_image(per, g, gc, gext, tx[lane], ty[lane], tz[lane]));
             }
+            if constexpr (MIXED) {
+                if (lane < nv) {
+                    const int32_t j = tj[lane];
+                    trec1[lane] = rec1[j];
+                    trec2[lane] = rec2[j];
+                    trm[lane] = a.fm[j];
+                }
+            }
+            cand_tested += (unsigned long long)nv;
             __syncthreads();
             auto tile = [&](auto wrap_tag) {
                 constexpr bool WRAP = decltype(wrap_tag)::value;
                 // r = 0 pairs (the particle itself, or a coincident one) count as
                 // neighbours but exert no force and no heating (x_ij = 0): they
                 // are accepted here and skipped in the interaction
+                const R hi2 = WRAP ? Hi2w : Hi2;
                 auto in = [&](uint32_t b, R x, R y, R z, R h2) -> uint32_t {
                     R dx, dy, dz;
                     const R r2 = pair_r2<MIXED, WRAP, R>(x, y, z, qx, qy, qz, per, g, Lf, hLf,
                                                          dx, dy, dz);
-                    const R hi2 = WRAP ? Hi2w : Hi2;
+                    if (MIXED && WRAP) h2 *= wfac;
                     return push_hit(b, r2, hi2 > h2 ? hi2 : h2);
                 };
                 struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
@@ -1317,7 +1439,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                     }
                     return b;
                 }, [&](int s, int k) {
-                    return PF{s, tx[k], ty[k], tz[k], tm[k], tv[k], tq[k], sp[s], sv[s], sq[s]};
+                    if constexpr (MIXED)
+                        return PF{s, tx[k], ty[k], tz[k], trm[k], trec1[k], trec2[k], sp[s], sv[s],
+                                  sq[s]};
+                    const int32_t j = tj[k];
+                    return PF{s, tx[k], ty[k], tz[k], (R)a.ms[j], rec1[j], rec2[j], sp[s], sv[s],
+                              sq[s]};
                 }, [&](const PF &d, bool valid, bool decided) -> bool {
                     const int s = d.s;
                     const V4<R> &cv = d.cv, &cq = d.cq, &ip = d.ip, &iv = d.iv, &iq = d.iq;
@@ -1392,6 +1519,64 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 4
                 acc_d[q] += acc[q][lane];
                 acc[q][lane] = 0;
             }
+        };
+        // Candidates are loaded 64 slots at a time; those that no sink's ball
+        // reaches and whose own ball reaches no sink are dropped, the rest
+        // appended to the queue, and each full half of it is a tile (one call
+        // site of the tile code: the loop flushes the last partial tile
+        // itself, before the walk refines again, whose stage shares this LDS).
+        // the next load's slot is fetched while this one is filtered
+        auto load_slot = [&](int t) -> Slot {
+            const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
+                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+            if (j < 0) return Slot{-1, 0.0, 0.0, 0.0, 0.0};
+            return Slot{j, a.xs[j], a.ys[j], a.zs[j], a.Hs[j]};
+        };
+        Slot nxt = nload > 0 ? load_slot(0) : Slot{-1, 0.0, 0.0, 0.0, 0.0};
+        for (int t = 0;;) {
+          if (t < nload) {
+            const Slot cur = nxt;
+            const int64_t j = cur.j;
+            ++t;
+            if (t < nload) nxt = load_slot(t);
+            R px = R(0), py = R(0), pz = R(0), ph2 = R(0);
+            bool keep = false;
+            if (j >= 0) {
+                double d0 = cur.x - gc[0], d1 = cur.y - gc[1], d2 = cur.z - gc[2];
+                if (per) {
+                    d0 = min_image(d0, g.L[0], g.halfL[0]);
+                    d1 = min_image(d1, g.L[1], g.halfL[1]);
+                    d2 = min_image(d2, g.L[2], g.halfL[2]);
+                }
+                const double Hj = cur.w;
+                keep = fil.inside_fs((float)d0, (float)d1, (float)d2, (float)Hj);
+                if constexpr (MIXED) {
+                    px = (R)d0; py = (R)d1; pz = (R)d2;
+                    const R hj = (R)Hj;
+                    ph2 = hj * hj * band1;
+                } else {
+                    px = cur.x; py = cur.y; pz = cur.z;
+                    ph2 = Hj * Hj;
+                }
+            }
+            const uint64_t kb = __ballot(keep);
+            if (keep) {
+                const int at = (qb + qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                               (uint32_t)(kb >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u))) &
+                               (kQueue - 1);
+                qx_[at] = px; qy_[at] = py; qz_[at] = pz; qh2_[at] = ph2;
+                qj_[at] = (int32_t)j;
+            }
+            qn += __popcll(kb);
+          }
+          if (qn >= kWave || (t >= nload && qn > 0)) {
+            const int nv = qn < kWave ? qn : kWave;
+            run_tile(nv);
+            qb ^= kWave;
+            qn -= nv;
+          }
+          if (t >= nload && qn == 0) break;
         }
         if (ws.nstack == 0) break;
         ws.ncand = 0;
@@ -1549,6 +1734,7 @@ inline SweepArgs base_args(Ctx *c) {
     a.Hs = c->Hs; a.rhos = c->rhos; a.oms = c->oms;
     a.vxs = c->vxs; a.vys = c->vys; a.vzs = c->vzs; a.As = c->As; a.css = c->css;
     a.frec1 = c->frec1; a.frec2 = c->frec2; a.fm = c->fm;
+    a.drec1 = c->drec1; a.drec2 = c->drec2;
     a.wstack = c->d_wstack;
     a.cnt = c->d_cnt;
     a.B = c->bucket;
