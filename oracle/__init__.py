@@ -70,8 +70,9 @@ def configure(L):
                               POINTER(c_int32), POINTER(c_int64)]
     L.orc_solve_h.restype = c_int
     L.orc_eos.argtypes = [pp, c_int64, dp, dp, dp, dp]
-    L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [ip, c_int64] + [dp] * 5 + [ip]
+    L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [ip, c_int64] + [dp] * 5 + [ip, dp]
     L.orc_forces.restype = c_int
+    L.orc_isentrope.argtypes = [pp, c_int64, dp, dp, dp, dp]
     if L.orc_params_size() != ctypes.sizeof(Params):
         raise RuntimeError("oracle parameter layout mismatch")
     return L
@@ -110,8 +111,11 @@ class Params(ctypes.Structure):
         ("gamma", c_double), ("P0", c_double),
         ("alpha", c_double), ("beta", c_double), ("eps_av", c_double),
         ("eta_c", c_double), ("eta_a", c_double), ("dt_max", c_double),
-        ("h_max", c_double), ("nr_tol", c_double),
+        ("h_max", c_double), ("nr_tol", c_double), ("flags", c_int32), ("pad_", c_int32),
     ]
+
+
+ENTROPY, EVOLVED = 1, 2
 
 
 def make_params(p: dict) -> Params:
@@ -139,6 +143,7 @@ def make_params(p: dict) -> Params:
     q.dt_max = float(p.get("dt_max", 1.0))
     q.h_max = float(p.get("h_max", 0.25))
     q.nr_tol = float(p.get("oracle_nr_tol", 1e-14))
+    q.flags = (ENTROPY if p.get("entropy") else 0) | (EVOLVED if p.get("evolved") else 0)
     return q
 
 
@@ -277,14 +282,25 @@ def forces(params: dict, x, y, z, vx, vy, vz, m, H, rho, omega, P, c, rows=None)
     n = len(x)
     ins = [_d(v) for v in (x, y, z, vx, vy, vz, m, H, rho, omega, P, c)]
     rr, rowp, nw = _rows(rows, n)
-    outs = [_d(np.zeros(nw)) for _ in range(5)]
+    outs = [_d(np.zeros(nw)) for _ in range(6)]
     cnt, cp = _i(np.zeros(nw, dtype=np.int64))
     rc = lib().orc_forces(ctypes.byref(Pp), n, *[a[1] for a in ins], rowp, nw,
-                          *[o[1] for o in outs], cp)
+                          *[o[1] for o in outs[:5]], cp, outs[5][1])
     if rc != 0:
         raise RuntimeError("oracle forces failed")
-    ax, ay, az, dudt, dti = (o[0] for o in outs)
-    return {"ax": ax, "ay": ay, "az": az, "dudt": dudt, "dt": dti, "count": cnt}
+    ax, ay, az, dudt, dti, drho = (o[0] for o in outs)
+    return {"ax": ax, "ay": ay, "az": az, "dudt": dudt, "dt": dti, "count": cnt, "drho": drho}
+
+
+def isentrope(params: dict, rho_old, u_old, rho_new):
+    """u(rho_new, s(rho_old, u_old)): the entropy-conserving update (Sec. 2.3.5)."""
+    P = make_params(params)
+    ro, rop = _d(rho_old)
+    uo, uop = _d(u_old)
+    rn, rnp = _d(rho_new)
+    un, unp = _d(np.zeros_like(ro))
+    lib().orc_isentrope(ctypes.byref(P), ro.size, rop, uop, rnp, unp)
+    return un
 
 
 # ---------------------------------------------------------------------------
@@ -304,7 +320,8 @@ STATE_KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H")
 
 
 def init(params: dict, state: dict) -> dict:
-    """Density and forces at the initial time; fills rho, omega, P, c, a, dudt, dt."""
+    """Density and forces at the initial time; fills rho, omega, P, c, a, dudt, dt
+    (and, for the entropy-conserving update, rho_old; for evolved density, drho)."""
     s = {k: np.array(state[k], dtype=np.float64, copy=True) for k in STATE_KEYS}
     d = solve_h(params, s["x"], s["y"], s["z"], s["m"], s["H"])
     s["H"], s["rho"], s["omega"] = d["H"], d["rho"], d["omega"]
@@ -312,8 +329,10 @@ def init(params: dict, state: dict) -> dict:
     s["P"], s["c"] = eos(params, s["rho"], s["u"])
     f = forces(params, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], s["H"],
                s["rho"], s["omega"], s["P"], s["c"])
-    for k in ("ax", "ay", "az", "dudt", "dt"):
+    for k in ("ax", "ay", "az", "dudt", "dt", "drho"):
         s[k] = f[k]
+    if params.get("entropy"):
+        s["rho_old"] = s["rho"].copy()
     s["n_d"] = int(d["count"].sum())
     s["n_f"] = int(f["count"].sum())
     return s
@@ -333,32 +352,52 @@ def _wrap(params: dict, v, a):
 
 
 def step(params: dict, s: dict, dt: float | None = None) -> dict:
-    """One kick-drift-kick step in place; returns the FP64 report."""
+    """One kick-drift-kick step in place; returns the FP64 report.
+
+    Entropy-conserving update (Sec. 2.3.5): du/dt holds only the viscous
+    heating; after the density pass the half-step u is carried along the
+    adiabat from the old to the new density (isentrope), then rho_old moves
+    on.  Evolved density (Sec. 2.3.3): rho is a state variable kicked and
+    predicted like u with d rho/dt from the force pass; the density pass only
+    supplies H and Omega."""
     if dt is None or dt <= 0:
         dt = global_dt(params, s)
     hdt = 0.5 * dt
+    evolved = bool(params.get("evolved"))
     vxh = s["vx"] + hdt * s["ax"]
     vyh = s["vy"] + hdt * s["ay"]
     vzh = s["vz"] + hdt * s["az"]
     uh = s["u"] + hdt * s["dudt"]
+    if evolved:
+        rhoh = s["rho"] + hdt * s["drho"]
     s["x"] = _wrap(params, s["x"] + dt * vxh, 0)
     s["y"] = _wrap(params, s["y"] + dt * vyh, 1)
     s["z"] = _wrap(params, s["z"] + dt * vzh, 2)
     d = solve_h(params, s["x"], s["y"], s["z"], s["m"], s["H"])
-    s["H"], s["rho"], s["omega"] = d["H"], d["rho"], d["omega"]
+    s["H"], s["omega"] = d["H"], d["omega"]
+    if evolved:
+        rho_f = rhoh + hdt * s["drho"]
+    else:
+        s["rho"] = d["rho"]
+        rho_f = s["rho"]
+    if params.get("entropy"):
+        uh = isentrope(params, s["rho_old"], uh, s["rho"])
+        s["rho_old"] = s["rho"].copy()
     vxp = vxh + hdt * s["ax"]
     vyp = vyh + hdt * s["ay"]
     vzp = vzh + hdt * s["az"]
     up = uh + hdt * s["dudt"]
-    s["P"], s["c"] = eos(params, s["rho"], up)
+    s["P"], s["c"] = eos(params, rho_f, up)
     f = forces(params, s["x"], s["y"], s["z"], vxp, vyp, vzp, s["m"], s["H"],
-               s["rho"], s["omega"], s["P"], s["c"])
-    for k in ("ax", "ay", "az", "dudt", "dt"):
+               rho_f, s["omega"], s["P"], s["c"])
+    for k in ("ax", "ay", "az", "dudt", "dt", "drho"):
         s[k] = f[k]
     s["vx"] = vxh + hdt * s["ax"]
     s["vy"] = vyh + hdt * s["ay"]
     s["vz"] = vzh + hdt * s["az"]
     s["u"] = uh + hdt * s["dudt"]
+    if evolved:
+        s["rho"] = rhoh + hdt * s["drho"]
     s["n_noconv"] = d["n_noconv"]
     s["n_d"] = int(d["count"].sum())
     s["n_f"] = int(f["count"].sum())

@@ -16,6 +16,7 @@
  *   - equation of state                                (Sec. 2.3.1)
  *   - pressure force, PdV du/dt, artificial viscosity  (Sec. 2.3.5, eq:AV_heating)
  *   - acceleration and signal-velocity time-step limits (Sec. 2.3.6, eq:courant_condition)
+ *   - entropy-conserving update of u, evolved density  (Sec. 2.3.5, Sec. 2.3.3)
  * The kick-drift-kick sequence is composed in oracle/__init__.py.
  *
  * Conventions (readings of the paper, listed in the design notes):
@@ -55,7 +56,14 @@ typedef struct {
     double eta_c, eta_a, dt_max;/* time-step limits */
     double h_max;     /* cap on the support radius H */
     double nr_tol;    /* relative tolerance on H */
+    int32_t flags;    /* ORC_ENTROPY: du/dt without the PdV term (the isentropic
+                         change is applied by orc_isentrope); ORC_EVOLVED: the
+                         force pass also returns d rho / dt */
+    int32_t pad_;
 } orc_params;
+
+#define ORC_ENTROPY 1
+#define ORC_EVOLVED 2
 
 int orc_num_threads(void) {
 #ifdef _OPENMP
@@ -567,6 +575,27 @@ void orc_eos(const orc_params *p, int64_t n, const double *rho, const double *u,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Entropy-conserving update (Sec. 2.3.5): u_new = u(rho_new, s(rho_old,     */
+/* u_old)), the internal energy that keeps the entropy of (rho_old, u_old)    */
+/* at the new density.  Ideal gas (Springel & Hernquist 2002): P / rho^gamma  */
+/* is the entropy function, so u scales as rho^(gamma-1).  Stiffened gas      */
+/* P = (gamma-1) rho u - gamma P0: along an adiabat du = (P/rho^2) d rho,     */
+/* whose solution keeps (P + P0) / rho^gamma fixed, i.e.                      */
+/*   u - P0/rho  scales as rho^(gamma-1).                                     */
+/* ------------------------------------------------------------------------ */
+void orc_isentrope(const orc_params *p, int64_t n, const double *rho_old, const double *u_old,
+                   const double *rho_new, double *u_new) {
+    const double gm = p->gamma;
+    for (int64_t i = 0; i < n; ++i) {
+        const double ratio = pow(rho_new[i] / rho_old[i], gm - 1.0);
+        if (p->eos == 0)
+            u_new[i] = u_old[i] * ratio;
+        else
+            u_new[i] = (u_old[i] - p->P0 / rho_old[i]) * ratio + p->P0 / rho_new[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Forces (Sec. 2.3.5).  For j in F_i, with x_ij = x_i - x_j, v_ij = v_i -  */
 /* v_j, dW/dr(r, H_k) x_ij / r = G_k x_ij where G_k = sigma g(q_k) / H_k^5  */
 /* (zero when r >= H_k), and A_k = P_k / (Omega_k rho_k^2):                 */
@@ -581,11 +610,18 @@ void orc_eos(const orc_params *p, int64_t n, const double *rho, const double *u,
 /* dt_i = min(dt_a, dt_cfl, dt_max).                                        */
 /* ------------------------------------------------------------------------ */
 
+/* With ORC_ENTROPY the PdV term is left out of du/dt: the entropy-conserving */
+/* scheme (Sec. 2.3.5) changes u isentropically with the density instead      */
+/* (orc_isentrope) and integrates only the viscous heating.  With ORC_EVOLVED */
+/* the force pass also returns the continuity equation's rate of density     */
+/* change (Sec. 2.3.3, evolved density), in the grad-h form                  */
+/*   d rho_i/dt = (1/Omega_i) sum m_j (v_ij . x_ij) G_i.                     */
 int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                const double *z, const double *vx, const double *vy, const double *vz,
                const double *m, const double *H, const double *rho, const double *omega,
                const double *P, const double *c, const int64_t *which, int64_t nw,
-               double *ax, double *ay, double *az, double *dudt, double *dti, int64_t *count) {
+               double *ax, double *ay, double *az, double *dudt, double *dti, int64_t *count,
+               double *drho) {
     double L[3], hL[3];
     box_lengths(p, L, hL);
     double sig = orc_sigma(p->kernel);
@@ -648,7 +684,9 @@ int orc_forces(const orc_params *p, int64_t n, const double *x, const double *y,
                 if (-mu > mumax) mumax = -mu;
             }
             ax[k] = sax; ay[k] = say; az[k] = saz;
-            dudt[k] = A[i] * spdv + 0.5 * sav;
+            const double heat = 0.5 * sav;   /* viscous heating, eq:AV_heating */
+            dudt[k] = (p->flags & ORC_ENTROPY) ? heat : A[i] * spdv + heat;
+            if (drho) drho[k] = spdv / omega[i];
             count[k] = cnt;
             double amag = sqrt(sax * sax + say * say + saz * saz);
             double dt = p->dt_max;

@@ -31,7 +31,7 @@ MUTANTS = {
     "geometric_cbar": (
         "double cbar = 0.5 * (c[i] + c[j]);", "double cbar = sqrt(c[i] * c[j]);", "visc"),
     "full_viscous_heating": (
-        "dudt[k] = A[i] * spdv + 0.5 * sav;", "dudt[k] = A[i] * spdv + sav;", "visc"),
+        "const double heat = 0.5 * sav;", "const double heat = sav;", "visc"),
     "signal_term_alpha": (
         "double den = (1.0 + 0.6 * p->alpha) * c[i] + 0.6 * p->beta * mumax;",
         "double den = (1.0 + 0.6 * p->alpha) * c[i] + 0.6 * p->alpha * mumax;", "dt"),
