@@ -112,16 +112,32 @@ typedef struct {
     int32_t stack_limit; /* entries of the per-wavefront walk stack in use, 2..768 (0 = 768).
                             A walk that would outgrow it restarts as a test of every bucket
                             of the set; results do not change, only the cost. */
-    int32_t reserved;  /* must be 0 */
+    int32_t flags;     /* SPH_FLAG_* (0 = the plain scheme):
+                          SPH_FLAG_ENTROPY: entropy-conserving update of u (Sec. 2.3.5):
+                            du/dt holds only the viscous heating (eq:AV_heating); after
+                            each step's density pass u is carried along the adiabat from
+                            the previous density to the new one, u(rho_new, s(rho_old,
+                            u_old)), for the ideal gas (P/rho^gamma fixed) and the stiffened
+                            gas ((P + P0)/rho^gamma fixed).
+                          SPH_FLAG_EVOLVED: evolved density (Sec. 2.3.3): rho is a state
+                            variable kicked and predicted like u with the continuity rate
+                            d rho_i/dt = (1/Omega_i) sum m_j (v_ij . x_ij) G_i from the force
+                            pass (written to drhodt); the density pass still sets H and
+                            Omega.  Not combined with SPH_FLAG_ENTROPY. */
 } sph_params;
 
+enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2 };
+
 /* Caller-owned device arrays, n doubles each, caller particle order.
- * State: x y z (positions inside the periodic box), vx vy vz, m, u, H.
+ * State: x y z (positions inside the periodic box), vx vy vz, m, u, H (and
+ * rho with SPH_FLAG_EVOLVED).
  * Results written by the calls: rho, omega (grad-h term), P, c (pressure and
- * sound speed), ax ay az, dudt, dt (per-particle time-step limit). */
+ * sound speed), ax ay az, dudt, dt (per-particle time-step limit), drhodt
+ * (continuity rate; only with SPH_FLAG_EVOLVED, may be NULL otherwise). */
 typedef struct {
     double *x, *y, *z, *vx, *vy, *vz, *m, *u, *H;
     double *rho, *omega, *P, *c, *ax, *ay, *az, *dudt, *dt;
+    double *drhodt;
 } sph_particles;
 
 /* Counters of the most recent call, read with sph_get_stats. */
@@ -220,7 +236,10 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream);
  * minimum per-particle limit of the previous force pass, read on the device):
  * opening kick, drift with periodic wrap, tree build, density, predictor,
  * EOS, forces with the predicted v and u, closing kick, FP64 reductions.
- * Requires a previous sph_init or sph_step. */
+ * With SPH_FLAG_ENTROPY the half-step u moves along the adiabat to the new
+ * density right after the density pass (and the prediction of u with it);
+ * with SPH_FLAG_EVOLVED rho is kicked and predicted like u and the density
+ * pass leaves it untouched.  Requires a previous sph_init or sph_step. */
 sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream);
 
 /* Captures one sph_step (same arguments) into a HIP graph owned by the

@@ -44,12 +44,15 @@ class Params(ctypes.Structure):
         ("eta_c", c_double), ("eta_a", c_double), ("dt_max", c_double),
         ("h_max", c_double), ("oversel", c_double), ("nr_tol", c_double),
         ("nr_maxit", c_int32), ("bucket", c_int32), ("stack_limit", c_int32),
-        ("reserved", c_int32),
+        ("flags", c_int32),
     ]
 
 
+FLAG_ENTROPY, FLAG_EVOLVED = 1, 2
+
+
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H",
-          "rho", "omega", "P", "c", "ax", "ay", "az", "dudt", "dt")
+          "rho", "omega", "P", "c", "ax", "ay", "az", "dudt", "dt", "drhodt")
 
 
 class Particles(ctypes.Structure):
@@ -142,6 +145,7 @@ def make_params(p: dict) -> Params:
     for name in ("nr_maxit", "bucket", "stack_limit"):
         if name in p:
             setattr(q, name, int(p[name]))
+    q.flags = (FLAG_ENTROPY if p.get("entropy") else 0) | (FLAG_EVOLVED if p.get("evolved") else 0)
     return q
 
 

@@ -58,6 +58,7 @@ void free_all(Ctx &c) {
     c.allocs.clear();
     c.frec1 = c.frec2 = c.fm = nullptr;
     c.drec1 = c.drec2 = nullptr;
+    c.rho_old = c.rho_pred = c.rho_sum = c.drs = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
     if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
     if (c.h_flags) { (void)hipHostFree(c.h_flags); c.h_flags = nullptr; }
@@ -90,7 +91,11 @@ bool valid_params(const sph_params *p, std::string &why) {
     if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
         why = "stack_limit must be 0 or 2..768"; return false;
     }
-    if (p->reserved != 0) { why = "reserved must be 0"; return false; }
+    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED)) { why = "unknown flags"; return false; }
+    if ((p->flags & SPH_FLAG_ENTROPY) && (p->flags & SPH_FLAG_EVOLVED)) {
+        why = "the entropy-conserving update needs the summed density (not SPH_FLAG_EVOLVED)";
+        return false;
+    }
     return true;
 }
 
@@ -240,6 +245,8 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.vpx, n); A(c.vpy, n); A(c.vpz, n); A(c.upred, n);
     A(c.hprev, n);
     A(c.d_h0, n);
+    if (c.prm.flags & SPH_FLAG_ENTROPY) A(c.rho_old, n);
+    if (c.prm.flags & SPH_FLAG_EVOLVED) { A(c.rho_pred, n); A(c.rho_sum, n); A(c.drs, n); }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
@@ -279,6 +286,8 @@ sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs, int
     if (outputs && (!p->rho || !p->omega || !p->P || !p->c || !p->ax || !p->ay || !p->az ||
                     !p->dudt || !p->dt))
         return fail(x, SPH_ERR_INVALID, "an output array is NULL");
+    if (outputs && x && (x->c.prm.flags & SPH_FLAG_EVOLVED) && !p->drhodt)
+        return fail(x, SPH_ERR_INVALID, "drhodt is NULL (evolved density)");
     return SPH_OK;
 }
 
@@ -329,16 +338,19 @@ Cols cols0() {
     return k;
 }
 
-// Density pass on the current tree; H first guess from the caller.
-sph_status do_density(sph_ctx *x, sph_particles *p, hipStream_t s) {
+// Density pass on the current tree; H first guess from the caller.  Inside a
+// step with the evolved density the summed density goes to scratch: the
+// caller's rho is then a state variable.
+sph_status do_density(sph_ctx *x, sph_particles *p, hipStream_t s, bool in_step = false) {
     Ctx &c = x->c;
     Cols g = cols0();
     g.src[0] = p->H; g.dst[0] = c.Hs; g.n = 1;
     HIPCHK(x, launch_gather(&c, g, s), "gather H");
     HIPCHK(x, launch_density(&c, s), "density");
+    const bool keep_rho = in_step && (c.prm.flags & SPH_FLAG_EVOLVED);
     Cols o = cols0();
     o.src[0] = c.Hs; o.dst[0] = p->H;
-    o.src[1] = c.rhos; o.dst[1] = p->rho;
+    o.src[1] = c.rhos; o.dst[1] = keep_rho ? c.rho_sum : p->rho;
     o.src[2] = c.oms; o.dst[2] = p->omega;
     o.n = 3;
     HIPCHK(x, launch_scatter(&c, o, s), "scatter density");
@@ -346,16 +358,24 @@ sph_status do_density(sph_ctx *x, sph_particles *p, hipStream_t s) {
     return SPH_OK;
 }
 
-// Force pass; velocities and u from the given columns (caller order).
+// Force pass; velocities and u from the given columns (caller order).  The
+// density comes from the density pass, from the caller (gather_density) or,
+// with the evolved density inside a step, from the predicted density.
 sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const double *vy,
-                     const double *vz, const double *u, bool gather_density, hipStream_t s) {
+                     const double *vz, const double *u, bool gather_density, hipStream_t s,
+                     bool in_step = false) {
     Ctx &c = x->c;
+    const bool evolved = (c.prm.flags & SPH_FLAG_EVOLVED) != 0;
     Cols g = cols0();
     g.src[0] = vx; g.dst[0] = c.vxs;
     g.src[1] = vy; g.dst[1] = c.vys;
     g.src[2] = vz; g.dst[2] = c.vzs;
     g.src[3] = u; g.dst[3] = c.us;
     g.n = 4;
+    if (in_step && evolved) {
+        g.src[4] = c.rho_pred; g.dst[4] = c.rhos;
+        g.n = 5;
+    }
     if (gather_density) {
         g.src[4] = p->H; g.dst[4] = c.Hs;
         g.src[5] = p->rho; g.dst[5] = c.rhos;
@@ -373,6 +393,10 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
     o.src[3] = c.dus; o.dst[3] = p->dudt;
     o.src[4] = c.dts; o.dst[4] = p->dt;
     o.n = 5;
+    if (evolved) {
+        o.src[5] = c.drs; o.dst[5] = p->drhodt;
+        o.n = 6;
+    }
     HIPCHK(x, launch_scatter(&c, o, s), "scatter forces");
     return SPH_OK;
 }
@@ -383,9 +407,10 @@ sph_status do_step(sph_ctx *x, sph_particles *p, double dt, hipStream_t s) {
     HIPCHK(x, launch_set_dt(&c, dt, s), "dt");
     HIPCHK(x, launch_kick_drift(&c, p, s), "kick-drift");
     HIPCHK(x, launch_tree_build(&c, p, s), "tree");
-    sph_status st = do_density(x, p, s);
+    sph_status st = do_density(x, p, s, true);
     if (st != SPH_OK) return st;
-    st = do_forces(x, p, c.vpx, c.vpy, c.vpz, c.upred, false, s);
+    if (c.prm.flags & SPH_FLAG_ENTROPY) HIPCHK(x, launch_isentrope(&c, p, s), "isentrope");
+    st = do_forces(x, p, c.vpx, c.vpy, c.vpz, c.upred, false, s, true);
     if (st != SPH_OK) return st;
     HIPCHK(x, launch_closing_kick(&c, p, s), "closing kick");
     HIPCHK(x, launch_reduce(&c, p, s), "reduce");
@@ -636,6 +661,8 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
            "H history");
     st = do_density(ctx, p, s);
     if (st != SPH_OK) return st;
+    if (c.prm.flags & SPH_FLAG_ENTROPY)
+        HIPCHK(ctx, launch_copy(c.rho_old, p->rho, c.n, s), "rho_old");
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, false, s);
     if (st != SPH_OK) return st;
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
@@ -812,6 +839,7 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     if (n < 0) return SPH_ERR_INVALID;
     if (n > kNoAllocMaxN) return SPH_ERR_CAPACITY;   // beyond the static work space
     if (check_particles(nullptr, p, true, n) != SPH_OK) return SPH_ERR_INVALID;
+    if ((params->flags & SPH_FLAG_EVOLVED) && n > 0 && !p->drhodt) return SPH_ERR_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return SPH_ERR_HIP;
     if (dev < 0 || dev >= kNoAllocDevices) return SPH_ERR_INVALID;
@@ -887,6 +915,8 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     }
     cv.take(&c.axs, n); cv.take(&c.ays, n); cv.take(&c.azs, n); cv.take(&c.dus, n); cv.take(&c.dts, n);
     cv.take(&c.nodes, c.nnodes);
+    c.drs = nullptr;
+    if (c.prm.flags & SPH_FLAG_EVOLVED) cv.take(&c.drs, n);
     cv.take(&c.d_wstack, (size_t)c.ngroups * kStackCap);
     cv.take(&c.d_scan_tmp, c.scan_tmp_len);
     cv.take(&c.d_cnt, C_NCOUNTERS);

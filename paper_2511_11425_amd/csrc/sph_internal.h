@@ -116,6 +116,10 @@ struct Ctx {
     double *vpx = nullptr, *vpy = nullptr, *vpz = nullptr, *upred = nullptr;
     double *hprev = nullptr;   // caller order: converged H of the step before (0 = none)
     double *d_h0 = nullptr;    // caller order: the autotuner's copy of the first guess of H
+    double *rho_old = nullptr; // caller order: density of the last step (entropy-conserving update)
+    double *rho_pred = nullptr;// caller order: predicted density (evolved density)
+    double *rho_sum = nullptr; // caller order: summed density of a step (evolved density)
+    double *drs = nullptr;     // sorted: continuity rate of the force pass (evolved density)
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 
     // scan scratch
@@ -181,6 +185,8 @@ hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *
                       hipStream_t s);
 hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s);
 hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_isentrope(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s);
 hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s);
 hipError_t launch_set_dtnext(Ctx *c, const sph_particles *p, hipStream_t s);

@@ -157,11 +157,15 @@ __global__ __launch_bounds__(kThreads) void k_set_min_dt(const double *__restric
 //   v_half = v + (dt/2) a,  u_half = u + (dt/2) du      (stored in v, u)
 //   v_pred = v_half + (dt/2) a,  u_pred likewise          (scratch)
 //   x     += dt v_half, wrapped into the periodic box
+//   evolved density: rho_half = rho + (dt/2) drho (stored in rho),
+//                    rho_pred = rho_half + (dt/2) drho (scratch)
 struct KickArgs {
     double *x, *y, *z, *vx, *vy, *vz, *u;
     double *H, *Hprev;
     const double *ax, *ay, *az, *du;
     double *vpx, *vpy, *vpz, *up;
+    double *rho, *rhop;          // evolved density only (else null)
+    const double *drho;
     const SetGeom *sets;
     int nsets;
     int periodic;
@@ -193,6 +197,12 @@ __global__ void k_kick_drift(KickArgs a) {
     a.vpy[i] = vhy + hdt * ay;
     a.vpz[i] = vhz + hdt * az;
     a.up[i] = uh + hdt * du;
+    if (a.rho) {
+        const double dr = a.drho[i];
+        const double rh = a.rho[i] + hdt * dr;
+        a.rho[i] = rh;
+        a.rhop[i] = rh + hdt * dr;
+    }
     double nx = a.x[i] + dt * vhx;
     double ny = a.y[i] + dt * vhy;
     double nz = a.z[i] + dt * vhz;
@@ -212,12 +222,14 @@ __global__ void k_kick_drift(KickArgs a) {
     if (Hp > 0.0 && Hn > 0.0) a.H[i] = Hn * fmin(fmax(Hn / Hp, 0.95), 1.05);
 }
 
-// Closing kick: v = v_half + (dt/2) a_new, u likewise.
+// Closing kick: v = v_half + (dt/2) a_new, u likewise (and rho with the
+// evolved density).
 __global__ void k_closing_kick(int64_t n, const SetGeom *sets, int nsets,
                                const double *__restrict__ dtp, double *vx, double *vy,
                                double *vz, double *u, const double *__restrict__ ax,
                                const double *__restrict__ ay, const double *__restrict__ az,
-                               const double *__restrict__ du) {
+                               const double *__restrict__ du, double *rho,
+                               const double *__restrict__ drho) {
 #pragma clang fp contract(off)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -226,6 +238,34 @@ __global__ void k_closing_kick(int64_t n, const SetGeom *sets, int nsets,
     vy[i] = vy[i] + hdt * ay[i];
     vz[i] = vz[i] + hdt * az[i];
     u[i] = u[i] + hdt * du[i];
+    if (rho) rho[i] = rho[i] + hdt * drho[i];
+}
+
+// Entropy-conserving update (Sec. 2.3.5), after the density pass of a step:
+// the half-step u moves along the adiabat from the last step's density to
+// the new one, u(rho_new, s(rho_old, u)); ideal gas: u scales as
+// rho^(gamma-1) (Springel & Hernquist 2002); stiffened gas: u - P0/rho does
+// ((P + P0)/rho^gamma is its adiabatic invariant).  Then rho_old moves on and
+// the prediction of u is redone from the new half-step value.
+__global__ void k_isentrope(int64_t n, const SetGeom *sets, int nsets, const double *dtp,
+                            int eos, double gam, double P0, double *u, double *rho_old,
+                            const double *__restrict__ rho_new, const double *__restrict__ du,
+                            double *up) {
+#pragma clang fp contract(off)
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double hdt = 0.5 * dtp[nsets == 1 ? 0 : find_set_k(sets, nsets, i)];
+    const double r0 = rho_old[i], r1 = rho_new[i];
+    const double ratio = pow(r1 / r0, gam - 1.0);
+    const double uh = eos == SPH_EOS_IDEAL ? u[i] * ratio : (u[i] - P0 / r0) * ratio + P0 / r1;
+    u[i] = uh;
+    up[i] = uh + hdt * du[i];
+    rho_old[i] = r1;
+}
+
+__global__ void k_copy_f64(double *dst, const double *__restrict__ src, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 // Deterministic two-stage FP64 reduction: fixed grid, fixed tree order.
@@ -338,6 +378,10 @@ hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s) {
     a.H = p->H; a.Hprev = c->hprev;
     a.ax = p->ax; a.ay = p->ay; a.az = p->az; a.du = p->dudt;
     a.vpx = c->vpx; a.vpy = c->vpy; a.vpz = c->vpz; a.up = c->upred;
+    const bool evolved = (c->prm.flags & SPH_FLAG_EVOLVED) != 0;
+    a.rho = evolved ? p->rho : nullptr;
+    a.rhop = evolved ? c->rho_pred : nullptr;
+    a.drho = evolved ? p->drhodt : nullptr;
     a.sets = c->d_sets; a.nsets = c->nsets; a.periodic = c->prm.periodic;
     a.dt = c->d_dt; a.n = c->n;
     k_kick_drift<<<nblk(c->n, kThreads), kThreads, 0, s>>>(a);
@@ -346,9 +390,24 @@ hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s) {
 
 hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s) {
     if (c->n == 0) return hipSuccess;
-    k_closing_kick<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->d_sets, c->nsets, c->d_dt,
-                                                             p->vx, p->vy, p->vz, p->u, p->ax,
-                                                             p->ay, p->az, p->dudt);
+    const bool evolved = (c->prm.flags & SPH_FLAG_EVOLVED) != 0;
+    k_closing_kick<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->n, c->d_sets, c->nsets, c->d_dt, p->vx, p->vy, p->vz, p->u, p->ax, p->ay, p->az,
+        p->dudt, evolved ? p->rho : nullptr, evolved ? p->drhodt : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_isentrope(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_isentrope<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->n, c->d_sets, c->nsets, c->d_dt, c->prm.eos, c->prm.gamma, c->prm.P0, p->u,
+        c->rho_old, p->rho, p->dudt, c->upred);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    k_copy_f64<<<nblk(n, kThreads), kThreads, 0, s>>>(dst, src, n);
     return hipGetLastError();
 }
 

@@ -514,6 +514,8 @@ struct SweepArgs {
     const float *frec1, *frec2, *fm;   // mixed force records (see the EOS pass)
     const double *drec1, *drec2;       // FP64 force records
     double *ax, *ay, *az, *du, *dt;
+    double *drho;           // evolved density: continuity rate (sorted), else null
+    int entropy;            // du/dt without the PdV term (entropy-conserving update)
     unsigned long long *cnt;
     int B;
     int periodic;
@@ -1287,7 +1289,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     __shared__ R trm[MIXED ? kWave : 1];
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink: (x H) (v 1/H) (A c rho sigma/H^5)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
-    __shared__ double acc[4][kWave];   // a_x a_y a_z du/dt
+    __shared__ double acc[5][kWave];   // a_x a_y a_z du/dt, sum m (v_ij . x_ij) G_i
     __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
 
     const int lane = threadIdx.x;
@@ -1350,9 +1352,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                      (R)(act ? a.vzs[i] : 0.0), act ? R(1) / Hi : R(0)};
     const double hinv_i = act ? 1.0 / Hd : 0.0, h2_i = hinv_i * hinv_i;
     sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), (R)(sigma_of<K>() * h2_i * h2_i * hinv_i)};
-    for (int q = 0; q < 4; ++q) acc[q][lane] = 0;
+    for (int q = 0; q < 5; ++q) acc[q][lane] = 0;
     amu[lane] = 0;
     const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
+    const R pdv = a.entropy ? R(0) : R(1);   // PdV part of du/dt (off: entropy-conserving)
+    const bool evolved = a.drho != nullptr;
 
     Sink sk;
     sink_bounds(act, xi, Hd, sk);
@@ -1360,7 +1364,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     bool linear = false;
     int overflows = 0;
 
-    double acc_d[4] = {0, 0, 0, 0};
+    double acc_d[5] = {0, 0, 0, 0, 0};
     int cnt = 0;
     int rej = 0;       // accepted pairs that the FP64 re-test rejected (wave total)
     int retests = 0;   // pairs the wave re-tested in FP64
@@ -1373,7 +1377,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
             // restart the whole pass with the linear bucket test
             ++overflows;
             linear = true;
-            for (int q = 0; q < 4; ++q) acc_d[q] = 0;
+            for (int q = 0; q < 5; ++q) acc_d[q] = 0;
             cnt = 0;
             rej = 0;
             retests = 0;
@@ -1495,7 +1499,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                         atomicAdd(&acc[1][s], (double)(-sc_ * xy));
                         atomicAdd(&acc[2][s], (double)(-sc_ * xz));
                         // du/dt: A_i m_j G_i v.x + (1/2) m_j Pi Gbar v.x (A_i is the sink's)
-                        atomicAdd(&acc[3][s], (double)(mj * vdotx * (iq.x * Gi + R(0.5) * Pi * Gbar)));
+                        atomicAdd(&acc[3][s],
+                                  (double)(mj * vdotx * (pdv * iq.x * Gi + R(0.5) * Pi * Gbar)));
+                        if (evolved) atomicAdd(&acc[4][s], (double)(mj * vdotx * Gi));
                         if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
                     return false;
@@ -1515,7 +1521,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
             if (wrapf) tile(std::true_type{});
             else tile(std::false_type{});
             __syncthreads();
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < (evolved ? 5 : 4); ++q) {
                 acc_d[q] += acc[q][lane];
                 acc[q][lane] = 0;
             }
@@ -1600,6 +1606,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         if (!isfinite(amag) || !isfinite(den)) dtv = NAN;
         a.dt[i] = dtv;
         nonfinite = !isfinite(dtv) || !isfinite(acc_d[3]);
+        if (evolved) a.drho[i] = acc_d[4] / a.oms[i];
     }
     // the particle itself passed the distance test once (r = 0)
     int pairs_n = wave_sum_i(act ? cnt - 1 : 0) - rej;
@@ -1790,6 +1797,8 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
     if (c->ngroups == 0) return hipSuccess;
     SweepArgs a = base_args(c);
     a.ax = c->axs; a.ay = c->ays; a.az = c->azs; a.du = c->dus; a.dt = c->dts;
+    a.drho = (c->prm.flags & SPH_FLAG_EVOLVED) ? c->drs : nullptr;
+    a.entropy = (c->prm.flags & SPH_FLAG_ENTROPY) ? 1 : 0;
     mark(c, E_FOR0, s);
     hipError_t e = c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
                                                       : forces_dispatch<false>(c, a, s);
