@@ -73,6 +73,10 @@ def configure(L):
     L.orc_forces.argtypes = [pp, c_int64] + [dp] * 12 + [ip, c_int64] + [dp] * 5 + [ip, dp]
     L.orc_forces.restype = c_int
     L.orc_isentrope.argtypes = [pp, c_int64, dp, dp, dp, dp]
+    L.orc_imbalance.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, dp, c_double, ip, c_int64, dp]
+    L.orc_imbalance.restype = c_int
+    L.orc_ic_average.argtypes = [pp, c_int64, dp, dp, dp, dp, dp, dp, dp, ip, c_int64, dp, dp]
+    L.orc_ic_average.restype = c_int
     if L.orc_params_size() != ctypes.sizeof(Params):
         raise RuntimeError("oracle parameter layout mismatch")
     return L
@@ -292,6 +296,71 @@ def forces(params: dict, x, y, z, vx, vy, vz, m, H, rho, omega, P, c, rows=None)
     return {"ax": ax, "ay": ay, "az": az, "dudt": dudt, "dt": dti, "count": cnt, "drho": drho}
 
 
+def imbalance(params: dict, x, y, z, m, H, mat=None, alpha=None, rows=None):
+    """Kernel imbalance I_i (eq:Kernel_imbalance) at the given H (mat None:
+    one material; alpha defaults to params['ic_alpha'], else 10: the paper
+    gives no value; 10 puts I near 1.5 at the free surface of a uniform
+    body)."""
+    P = make_params(params)
+    n = len(x)
+    if alpha is None:
+        alpha = float(params.get("ic_alpha", 10.0))
+    ins = [_d(v) for v in (x, y, z, m, H)]
+    matp = None
+    if mat is not None:
+        mat_a = _d(mat)   # (kept alive until the call returns)
+        matp = mat_a[1]
+    rr, rp, nw = _rows(rows, n)
+    out, op = _d(np.zeros(nw))
+    rc = lib().orc_imbalance(ctypes.byref(P), n, *[a[1] for a in ins], matp, float(alpha), rp,
+                             nw, op)
+    if rc != 0:
+        raise RuntimeError("oracle imbalance failed")
+    return out
+
+
+def ic_average(params: dict, x, y, z, H, I, T, Pr, rows=None):
+    """Interface-correction averages (Tbar, Pbar) with weights exp(-I_j^2) W_ij(h_i)."""
+    P = make_params(params)
+    n = len(x)
+    ins = [_d(v) for v in (x, y, z, H, I, T, Pr)]
+    rr, rp, nw = _rows(rows, n)
+    tb, tbp = _d(np.zeros(nw))
+    pb, pbp = _d(np.zeros(nw))
+    rc = lib().orc_ic_average(ctypes.byref(P), n, *[a[1] for a in ins], rp, nw, tbp, pbp)
+    if rc != 0:
+        raise RuntimeError("oracle interface averages failed")
+    return tb, pb
+
+
+def rho_from_eos(params: dict, T, Pr):
+    """rho_EOS(T, P) with the temperature T = u (c_v = 1): ideal gas
+    P / ((gamma - 1) T), stiffened gas (P + gamma P0) / ((gamma - 1) T)."""
+    g = float(params.get("gamma", 5.0 / 3.0))
+    if params.get("eos", "ideal") in ("stiffened", 1):
+        return (Pr + g * float(params.get("P0", 0.0))) / ((g - 1.0) * T)
+    return Pr / ((g - 1.0) * T)
+
+
+def interface_correct(params: dict, x, y, z, m, H, mat, rho, u, Pr):
+    """Interface correction (Sec. 2.3.4) of the fluid values at the given H:
+    I from eq:Kernel_imbalance, (Tbar, Pbar), P~ = e P + (1 - e) Pbar and
+    T~ likewise with e = exp(-I^2), rho~ = rho_EOS(T~, P~) (the uncorrected
+    rho where that is not a positive number), c~ from the EOS at (rho~, T~).
+    T = u."""
+    I = imbalance(params, x, y, z, m, H, mat)
+    Tbar, Pbar = ic_average(params, x, y, z, H, I, u, Pr)
+    e = np.exp(-I * I)
+    Pc = e * Pr + (1.0 - e) * Pbar
+    Tc = e * u + (1.0 - e) * Tbar
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rc = rho_from_eos(params, Tc, Pc)
+    ok = np.isfinite(rc) & (rc > 0.0)
+    rc = np.where(ok, rc, rho)
+    _, cc = eos(params, rc, Tc)
+    return {"I": I, "Tbar": Tbar, "Pbar": Pbar, "P": Pc, "T": Tc, "rho": rc, "c": cc}
+
+
 def isentrope(params: dict, rho_old, u_old, rho_new):
     """u(rho_new, s(rho_old, u_old)): the entropy-conserving update (Sec. 2.3.5)."""
     P = make_params(params)
@@ -327,10 +396,17 @@ def init(params: dict, state: dict) -> dict:
     s["H"], s["rho"], s["omega"] = d["H"], d["rho"], d["omega"]
     s["n_noconv"] = d["n_noconv"]
     s["P"], s["c"] = eos(params, s["rho"], s["u"])
+    rho_f = s["rho"]
+    if params.get("interface"):
+        ic = interface_correct(params, s["x"], s["y"], s["z"], s["m"], s["H"], state.get("mat"),
+                               s["rho"], s["u"], s["P"])
+        rho_f, s["P"], s["c"], s["imb"], s["rho_c"] = ic["rho"], ic["P"], ic["c"], ic["I"], ic["rho"]
     f = forces(params, s["x"], s["y"], s["z"], s["vx"], s["vy"], s["vz"], s["m"], s["H"],
-               s["rho"], s["omega"], s["P"], s["c"])
+               rho_f, s["omega"], s["P"], s["c"])
     for k in ("ax", "ay", "az", "dudt", "dt", "drho"):
         s[k] = f[k]
+    if state.get("mat") is not None:
+        s["mat"] = np.array(state["mat"], dtype=np.float64, copy=True)
     if params.get("entropy"):
         s["rho_old"] = s["rho"].copy()
     s["n_d"] = int(d["count"].sum())
@@ -353,6 +429,9 @@ def _wrap(params: dict, v, a):
 
 def step(params: dict, s: dict, dt: float | None = None) -> dict:
     """One kick-drift-kick step in place; returns the FP64 report.
+
+    Interface correction (Sec. 2.3.4): after the EOS at the predicted u, the
+    force pass takes the corrected density, pressure and sound speed.
 
     Entropy-conserving update (Sec. 2.3.5): du/dt holds only the viscous
     heating; after the density pass the half-step u is carried along the
@@ -388,6 +467,10 @@ def step(params: dict, s: dict, dt: float | None = None) -> dict:
     vzp = vzh + hdt * s["az"]
     up = uh + hdt * s["dudt"]
     s["P"], s["c"] = eos(params, rho_f, up)
+    if params.get("interface"):
+        ic = interface_correct(params, s["x"], s["y"], s["z"], s["m"], s["H"], s.get("mat"),
+                               rho_f, up, s["P"])
+        rho_f, s["P"], s["c"], s["imb"], s["rho_c"] = ic["rho"], ic["P"], ic["c"], ic["I"], ic["rho"]
     f = forces(params, s["x"], s["y"], s["z"], vxp, vyp, vzp, s["m"], s["H"],
                rho_f, s["omega"], s["P"], s["c"])
     for k in ("ax", "ay", "az", "dudt", "dt", "drho"):

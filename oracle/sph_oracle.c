@@ -17,6 +17,7 @@
  *   - pressure force, PdV du/dt, artificial viscosity  (Sec. 2.3.5, eq:AV_heating)
  *   - acceleration and signal-velocity time-step limits (Sec. 2.3.6, eq:courant_condition)
  *   - entropy-conserving update of u, evolved density  (Sec. 2.3.5, Sec. 2.3.3)
+ *   - interface correction: kernel imbalance and averages (Sec. 2.3.4, eq:Kernel_imbalance)
  * The kick-drift-kick sequence is composed in oracle/__init__.py.
  *
  * Conventions (readings of the paper, listed in the design notes):
@@ -441,6 +442,94 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
             count[k] = v.count;
         }
         free(l.j); free(l.r2); free(mj); free(rj);
+    }
+    grid_free(&g);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interface correction (Sec. 2.3.4), at given H (h = H/2):                  */
+/* kernel imbalance (eq:Kernel_imbalance)                                   */
+/*   I_i = alpha |sum_j kappa_ij (x_j - x_i) m_j W_ij(h_i)|                 */
+/*         / (h_i sum_j m_j W_ij(h_i)),                                     */
+/* kappa_ij = +1 if i and j are of the same material, -1 otherwise (mat ==  */
+/* NULL: one material); x_j - x_i is the minimum image; the sums run over   */
+/* G_i and i itself (which adds only to the denominator).                   */
+/* ------------------------------------------------------------------------ */
+int orc_imbalance(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *m, const double *H, const double *mat,
+                  double alpha, const int64_t *which, int64_t nw, double *I) {
+    double L[3], hL[3];
+    box_lengths(p, L, hL);
+    grid g;
+    if (grid_build(&g, p, n, x, y, z, max_of(n, H)) != 0) return -1;
+    #pragma omp parallel
+    {
+        plist l = {0};
+        if (!which) nw = n;
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < nw; ++k) {
+            int64_t i = which ? which[k] : k;
+            grid_query(&g, p, L, hL, x, y, z, i, H[i], &l);
+            double f, gq;
+            shape(p->kernel, 0.0, &f, &gq);
+            double den = m[i] * f;   /* self term */
+            double nx = 0.0, ny = 0.0, nz = 0.0;
+            for (int64_t t = 0; t < l.n; ++t) {
+                int64_t j = l.j[t];
+                double dx, dy, dz;
+                double r2 = pair_d(p, L, hL, x, y, z, i, j, &dx, &dy, &dz);   /* d = x_j - x_i */
+                shape(p->kernel, sqrt(r2) / H[i], &f, &gq);
+                double w = m[j] * f;   /* W up to the common factor sigma / H_i^3 */
+                double kappa = (mat && mat[j] != mat[i]) ? -1.0 : 1.0;
+                den += w;
+                nx += kappa * w * dx;
+                ny += kappa * w * dy;
+                nz += kappa * w * dz;
+            }
+            I[k] = alpha * sqrt(nx * nx + ny * ny + nz * nz) / (0.5 * H[i] * den);
+        }
+        free(l.j); free(l.r2);
+    }
+    grid_free(&g);
+    return 0;
+}
+
+/* Interface-correction averages (Sec. 2.3.4): with w_ij = exp(-I_j^2)      */
+/* W_ij(h_i) over G_i and i itself,                                         */
+/*   Tbar_i = sum_j w_ij T_j / sum_j w_ij,   Pbar_i likewise.               */
+int orc_ic_average(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *H, const double *I, const double *T,
+                   const double *P, const int64_t *which, int64_t nw, double *Tbar,
+                   double *Pbar) {
+    double L[3], hL[3];
+    box_lengths(p, L, hL);
+    grid g;
+    if (grid_build(&g, p, n, x, y, z, max_of(n, H)) != 0) return -1;
+    #pragma omp parallel
+    {
+        plist l = {0};
+        if (!which) nw = n;
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < nw; ++k) {
+            int64_t i = which ? which[k] : k;
+            grid_query(&g, p, L, hL, x, y, z, i, H[i], &l);
+            double f, gq;
+            shape(p->kernel, 0.0, &f, &gq);
+            double w = exp(-I[i] * I[i]) * f;   /* self term */
+            double sw = w, st = w * T[i], sp = w * P[i];
+            for (int64_t t = 0; t < l.n; ++t) {
+                int64_t j = l.j[t];
+                shape(p->kernel, sqrt(l.r2[t]) / H[i], &f, &gq);
+                w = exp(-I[j] * I[j]) * f;
+                sw += w;
+                st += w * T[j];
+                sp += w * P[j];
+            }
+            Tbar[k] = st / sw;
+            Pbar[k] = sp / sw;
+        }
+        free(l.j); free(l.r2);
     }
     grid_free(&g);
     return 0;
