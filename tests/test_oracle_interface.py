@@ -45,7 +45,7 @@ def layer_imbalance(orc, kernel, H_over_a, layer, alpha=1.0):
 
 def slab_lattice(n_side=24, kernel="wc4", H_over_a=3.1):
     c = si.perfect_lattice(n_side, kernel, 100.0)
-    s, p = c["state"], c["params"]
+    s, p = c["state"], dict(c["params"], ic_alpha=1.0)
     a = 1.0 / n_side
     s["H"] = np.full(len(s["x"]), H_over_a * a)
     mat = np.where((s["x"] >= 0.25) & (s["x"] < 0.75), 1.0, 0.0)
@@ -86,7 +86,7 @@ def test_two_material_lattice_layers(orc, kernel):
 def surface_error(orc, kernel="wc2", H_over_a=2.6):
     n_side = 14
     c = si.perfect_lattice(n_side, kernel, 60.0)
-    s, p = c["state"], dict(c["params"], periodic=False)
+    s, p = c["state"], dict(c["params"], periodic=False, ic_alpha=1.0)
     a = 1.0 / n_side
     s["H"] = np.full(len(s["x"]), H_over_a * a)
     I = orc.imbalance(p, s["x"], s["y"], s["z"], s["m"], s["H"], None)
