@@ -123,21 +123,37 @@ typedef struct {
                             variable kicked and predicted like u with the continuity rate
                             d rho_i/dt = (1/Omega_i) sum m_j (v_ij . x_ij) G_i from the force
                             pass (written to drhodt); the density pass still sets H and
-                            Omega.  Not combined with SPH_FLAG_ENTROPY. */
+                            Omega.  Not combined with SPH_FLAG_ENTROPY.
+                          SPH_FLAG_INTERFACE: interface correction (Sec. 2.3.4) before
+                            every force pass: the kernel imbalance
+                            I_i = ic_alpha |sum_j kappa_ij (x_j - x_i) m_j W_ij(h_i)|
+                                  / (h_i sum_j m_j W_ij(h_i))  (eq:Kernel_imbalance;
+                            kappa = +1 within a material, -1 across, h = H/2, the sums
+                            over G_i and i), averages Tbar, Pbar of T = u and P with
+                            weights exp(-I_j^2) W_ij(h_i), the corrected P~ and T~ and
+                            rho~ = rho_EOS(T~, P~); the force pass uses rho~, P~ and the
+                            sound speed at (rho~, T~).  Not combined with SPH_FLAG_EVOLVED. */
+    double ic_alpha;   /* normalisation alpha of the kernel imbalance (the paper gives no
+                          value).  Default 10 (I near 1.5 at the free surface of a
+                          uniform body). */
 } sph_params;
 
-enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2 };
+enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4 };
 
 /* Caller-owned device arrays, n doubles each, caller particle order.
  * State: x y z (positions inside the periodic box), vx vy vz, m, u, H (and
  * rho with SPH_FLAG_EVOLVED).
  * Results written by the calls: rho, omega (grad-h term), P, c (pressure and
  * sound speed), ax ay az, dudt, dt (per-particle time-step limit), drhodt
- * (continuity rate; only with SPH_FLAG_EVOLVED, may be NULL otherwise). */
+ * (continuity rate; only with SPH_FLAG_EVOLVED, may be NULL otherwise).
+ * Interface correction (SPH_FLAG_INTERFACE): mat holds each particle's
+ * material id (integer values; NULL = one material); imb and rhoc receive the
+ * kernel imbalance and the corrected density (each may be NULL). */
 typedef struct {
     double *x, *y, *z, *vx, *vy, *vz, *m, *u, *H;
     double *rho, *omega, *P, *c, *ax, *ay, *az, *dudt, *dt;
     double *drhodt;
+    double *mat, *imb, *rhoc;
 } sph_particles;
 
 /* Counters of the most recent call, read with sph_get_stats. */
@@ -223,9 +239,9 @@ sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int
 sph_status sph_density(sph_ctx *ctx, sph_particles *p, void *stream);
 
 /* Force pass (Sec. 2.3.5, 2.3.6) on the current tree and H: EOS from rho and
- * u (written to P, c), then a, du/dt (pressure + viscosity) and the
- * per-particle limit dt = min(eta_a sqrt(H/|a|), Courant limit, dt_max).
- * Uses v and u as given. */
+ * u (written to P, c; with SPH_FLAG_INTERFACE the corrected values of Sec.
+ * 2.3.4), then a, du/dt (pressure + viscosity) and the per-particle limit
+ * dt = min(eta_a sqrt(H/|a|), Courant limit, dt_max).  Uses v and u as given. */
 sph_status sph_forces(sph_ctx *ctx, sph_particles *p, void *stream);
 
 /* Start-up: sph_build_tree(n) + density + forces at the initial time, and the

@@ -44,15 +44,16 @@ class Params(ctypes.Structure):
         ("eta_c", c_double), ("eta_a", c_double), ("dt_max", c_double),
         ("h_max", c_double), ("oversel", c_double), ("nr_tol", c_double),
         ("nr_maxit", c_int32), ("bucket", c_int32), ("stack_limit", c_int32),
-        ("flags", c_int32),
+        ("flags", c_int32), ("ic_alpha", c_double),
     ]
 
 
-FLAG_ENTROPY, FLAG_EVOLVED = 1, 2
+FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE = 1, 2, 4
 
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H",
-          "rho", "omega", "P", "c", "ax", "ay", "az", "dudt", "dt", "drhodt")
+          "rho", "omega", "P", "c", "ax", "ay", "az", "dudt", "dt", "drhodt", "mat", "imb",
+          "rhoc")
 
 
 class Particles(ctypes.Structure):
@@ -139,13 +140,14 @@ def make_params(p: dict) -> Params:
         q.box_lo[a] = float(lo[a])
         q.box_hi[a] = float(hi[a])
     for name in ("gamma", "P0", "alpha", "beta", "eps_av", "eta_c", "eta_a", "dt_max", "h_max",
-                 "oversel", "nr_tol"):
+                 "oversel", "nr_tol", "ic_alpha"):
         if name in p:
             setattr(q, name, float(p[name]))
     for name in ("nr_maxit", "bucket", "stack_limit"):
         if name in p:
             setattr(q, name, int(p[name]))
-    q.flags = (FLAG_ENTROPY if p.get("entropy") else 0) | (FLAG_EVOLVED if p.get("evolved") else 0)
+    q.flags = ((FLAG_ENTROPY if p.get("entropy") else 0) | (FLAG_EVOLVED if p.get("evolved") else 0)
+               | (FLAG_INTERFACE if p.get("interface") else 0))
     return q
 
 

@@ -59,6 +59,7 @@ void free_all(Ctx &c) {
     c.frec1 = c.frec2 = c.fm = nullptr;
     c.drec1 = c.drec2 = nullptr;
     c.rho_old = c.rho_pred = c.rho_sum = c.drs = nullptr;
+    c.mats = c.imbs = c.tbar = c.pbar = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
     if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
     if (c.h_flags) { (void)hipHostFree(c.h_flags); c.h_flags = nullptr; }
@@ -91,7 +92,16 @@ bool valid_params(const sph_params *p, std::string &why) {
     if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
         why = "stack_limit must be 0 or 2..768"; return false;
     }
-    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED)) { why = "unknown flags"; return false; }
+    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED | SPH_FLAG_INTERFACE)) {
+        why = "unknown flags"; return false;
+    }
+    if ((p->flags & SPH_FLAG_INTERFACE) && (p->flags & SPH_FLAG_EVOLVED)) {
+        why = "the interface correction applies to the summed density (not SPH_FLAG_EVOLVED)";
+        return false;
+    }
+    if ((p->flags & SPH_FLAG_INTERFACE) && !(p->ic_alpha > 0.0)) {
+        why = "ic_alpha must be positive"; return false;
+    }
     if ((p->flags & SPH_FLAG_ENTROPY) && (p->flags & SPH_FLAG_EVOLVED)) {
         why = "the entropy-conserving update needs the summed density (not SPH_FLAG_EVOLVED)";
         return false;
@@ -247,6 +257,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     A(c.d_h0, n);
     if (c.prm.flags & SPH_FLAG_ENTROPY) A(c.rho_old, n);
     if (c.prm.flags & SPH_FLAG_EVOLVED) { A(c.rho_pred, n); A(c.rho_sum, n); A(c.drs, n); }
+    if (c.prm.flags & SPH_FLAG_INTERFACE) { A(c.mats, n); A(c.imbs, n); A(c.tbar, n); A(c.pbar, n); }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
@@ -384,7 +395,23 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
     }
     HIPCHK(x, launch_gather(&c, g, s), "gather force inputs");
     if (gather_density) HIPCHK(x, launch_refit(&c, s), "refit");
+    const bool ic = (c.prm.flags & SPH_FLAG_INTERFACE) != 0;
+    if (ic) {
+        // interface correction (Sec. 2.3.4): materials in sorted order, the
+        // kernel imbalance, EOS, the averages, the corrected fluid values
+        c.mats_has = p->mat != nullptr;
+        if (c.mats_has) {
+            Cols mcol = cols0();
+            mcol.src[0] = p->mat; mcol.dst[0] = c.mats; mcol.n = 1;
+            HIPCHK(x, launch_gather(&c, mcol, s), "gather materials");
+        }
+        HIPCHK(x, launch_interface_sums(&c, 0, s), "kernel imbalance");
+    }
     HIPCHK(x, launch_eos(&c, c.us, p->P, p->c, s), "eos");
+    if (ic) {
+        HIPCHK(x, launch_interface_sums(&c, 1, s), "interface averages");
+        HIPCHK(x, launch_ic_correct(&c, p->P, p->c, p->imb, p->rhoc, s), "interface correction");
+    }
     HIPCHK(x, launch_forces(&c, s), "forces");
     Cols o = cols0();
     o.src[0] = c.axs; o.dst[0] = p->ax;
@@ -496,6 +523,7 @@ void sph_default_params(sph_params *p) {
     p->nr_tol = 0.0;
     p->nr_maxit = 64;
     p->bucket = 32;
+    p->ic_alpha = 10.0;
 }
 
 const char *sph_version(void) { return kVersion; }
@@ -917,6 +945,10 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     cv.take(&c.nodes, c.nnodes);
     c.drs = nullptr;
     if (c.prm.flags & SPH_FLAG_EVOLVED) cv.take(&c.drs, n);
+    c.mats = c.imbs = c.tbar = c.pbar = nullptr;
+    if (c.prm.flags & SPH_FLAG_INTERFACE) {
+        cv.take(&c.mats, n); cv.take(&c.imbs, n); cv.take(&c.tbar, n); cv.take(&c.pbar, n);
+    }
     cv.take(&c.d_wstack, (size_t)c.ngroups * kStackCap);
     cv.take(&c.d_scan_tmp, c.scan_tmp_len);
     cv.take(&c.d_cnt, C_NCOUNTERS);

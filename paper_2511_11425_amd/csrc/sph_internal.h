@@ -120,6 +120,9 @@ struct Ctx {
     double *rho_pred = nullptr;// caller order: predicted density (evolved density)
     double *rho_sum = nullptr; // caller order: summed density of a step (evolved density)
     double *drs = nullptr;     // sorted: continuity rate of the force pass (evolved density)
+    // interface correction (sorted): material ids, imbalance, averages
+    double *mats = nullptr, *imbs = nullptr, *tbar = nullptr, *pbar = nullptr;
+    bool mats_has = false;     // the caller gave material ids
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 
     // scan scratch
@@ -170,6 +173,7 @@ hipError_t launch_forces(Ctx *c, hipStream_t s);
 hipError_t launch_neighbors(Ctx *c, int mode, int64_t *row_count_caller, const int64_t *offsets,
                             int32_t *idx, hipStream_t s);
 hipError_t launch_sort_rows(Ctx *c, const int64_t *offsets, int32_t *idx, hipStream_t s);
+hipError_t launch_interface_sums(Ctx *c, int mode, hipStream_t s);   // 0 imbalance, 1 averages
 
 // Elementwise, step, reductions (sph_kdk.hip)
 constexpr int kMaxCols = 8;
@@ -186,6 +190,8 @@ hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *
 hipError_t launch_kick_drift(Ctx *c, sph_particles *p, hipStream_t s);
 hipError_t launch_closing_kick(Ctx *c, sph_particles *p, hipStream_t s);
 hipError_t launch_isentrope(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_ic_correct(Ctx *c, double *P_caller, double *c_caller, double *imb_caller,
+                             double *rho_caller, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s);
 hipError_t launch_set_dt(Ctx *c, double dt, hipStream_t s);

@@ -51,7 +51,7 @@ __global__ void k_scatter_cols(const uint32_t *__restrict__ perm, int64_t n, Col
 
 // EOS on sorted arrays: P, c and A = P / (Omega rho^2); P and c also go to
 // the caller's arrays.
-struct ForceRecords {   // mixed path only (rec1 == nullptr otherwise)
+struct ForceRecords {   // per-particle records the force pass reads (one path's are null)
     const double *m, *H, *vx, *vy, *vz;
     float *rec1, *rec2, *fm;     // mixed path
     double *drec1, *drec2;       // FP64 path
@@ -96,6 +96,51 @@ __global__ void k_eos(const uint32_t *__restrict__ perm, int64_t n, int eos, dou
     uint32_t i = perm[k];
     Pc[i] = P;
     cc[i] = c;
+}
+
+// Interface correction (Sec. 2.3.4), after the EOS pass and the two gather
+// sums, in sorted order: with e = exp(-I^2) and T = u (c_v = 1),
+//   P~ = e P + (1 - e) Pbar,  T~ = e T + (1 - e) Tbar,
+//   rho~ = rho_EOS(T~, P~): ideal P~/((gamma-1) T~), stiffened
+//          (P~ + gamma P0)/((gamma-1) T~); the uncorrected rho where that is
+//          not a positive number;
+//   c~ from the EOS at (rho~, T~), A = P~/(Omega rho~^2).
+// The force pass then reads rho~, P~, c~ and A (and their FP32 or FP64
+// records); the caller gets P~, c~, I and rho~.
+__global__ void k_ic_correct(const uint32_t *__restrict__ perm, int64_t n, int eos, double gam,
+                             double P0, double *rho, const double *__restrict__ u,
+                             const double *__restrict__ om, double *Ps, double *cs, double *As,
+                             const double *__restrict__ imb, const double *__restrict__ tbar,
+                             const double *__restrict__ pbar, double *Pc, double *cc,
+                             double *imb_c, double *rho_c, ForceRecords fr) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double I = imb[k];
+    const double e = exp(-I * I);
+    const double P = e * Ps[k] + (1.0 - e) * pbar[k];
+    const double T = e * u[k] + (1.0 - e) * tbar[k];
+    double r = eos == SPH_EOS_IDEAL ? P / ((gam - 1.0) * T) : (P + gam * P0) / ((gam - 1.0) * T);
+    if (!(r > 0.0) || !isfinite(r)) r = rho[k];
+    const double c2 = eos == SPH_EOS_IDEAL ? gam * (gam - 1.0) * T : gam * (P + P0) / r;
+    const double c = c2 > 0.0 ? sqrt(c2) : 0.0;
+    const double A = P / (om[k] * r * r);
+    rho[k] = r;
+    Ps[k] = P;
+    cs[k] = c;
+    As[k] = A;
+    if (fr.rec1) {
+        float4 *r2 = reinterpret_cast<float4 *>(fr.rec2);
+        r2[k] = make_float4((float)(1.0 / fr.H[k]), (float)A, (float)c, (float)r);
+    }
+    if (fr.drec1) {
+        double4 *r2 = reinterpret_cast<double4 *>(fr.drec2);
+        r2[k] = make_double4(1.0 / fr.H[k], A, c, r);
+    }
+    const uint32_t i = perm[k];
+    Pc[i] = P;
+    cc[i] = c;
+    if (imb_c) imb_c[i] = I;
+    if (rho_c) rho_c[i] = r;
 }
 
 // Step size of every set: the given dt, else the set's smallest per-particle
@@ -354,6 +399,17 @@ hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *
     k_eos<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->n, c->prm.eos, c->prm.gamma,
                                                     c->prm.P0, c->rhos, u_sorted, c->oms, c->Ps,
                                                     c->css, c->As, P_caller, c_caller, fr);
+    return hipGetLastError();
+}
+
+hipError_t launch_ic_correct(Ctx *c, double *P_caller, double *c_caller, double *imb_caller,
+                             double *rho_caller, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    ForceRecords fr{c->ms, c->Hs, c->vxs, c->vys, c->vzs, c->frec1, c->frec2, c->fm,
+                    c->drec1, c->drec2};
+    k_ic_correct<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->d_perm[0], c->n, c->prm.eos, c->prm.gamma, c->prm.P0, c->rhos, c->us, c->oms, c->Ps,
+        c->css, c->As, c->imbs, c->tbar, c->pbar, P_caller, c_caller, imb_caller, rho_caller, fr);
     return hipGetLastError();
 }
 

@@ -515,6 +515,13 @@ struct SweepArgs {
     const double *drec1, *drec2;       // FP64 force records
     double *ax, *ay, *az, *du, *dt;
     double *drho;           // evolved density: continuity rate (sorted), else null
+    // interface correction (sorted): material ids (null: one material),
+    // imbalance, u and P of the EOS pass, the averages, normalisation alpha
+    const double *mats;
+    double *imb;
+    const double *us, *Ps_;
+    double *tbar, *pbar;
+    double ic_alpha;
     int entropy;            // du/dt without the PdV term (entropy-conserving update)
     unsigned long long *cnt;
     int B;
@@ -1623,6 +1630,224 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     }
 }
 
+// ================================================================ interface correction
+//
+// Two gather sums at the converged H for the interface correction (Sec.
+// 2.3.4), with the density pass's walk, refinement, candidate filter, queue
+// and pair compaction (one scan, no iteration):
+//   MODE 0, kernel imbalance (eq:Kernel_imbalance): per sink, over G_i and i,
+//     D = sum m_j f(q),  N = sum kappa_ij m_j f(q) (x_j - x_i),
+//     I = alpha |N| / (h D) with h = H/2 (the factor sigma/H^3 of W cancels);
+//   MODE 1, averages: w_ij = exp(-I_j^2) f(q), Tbar = sum w T_j / sum w,
+//     Pbar = sum w P_j / sum w.
+// Both sums vanish continuously at the support (f(1) = 0), so the mixed path
+// needs no FP64 re-test near it.
+template <int K, bool MIXED, int MODE>
+__global__ __launch_bounds__(kWave) void k_gather_sums(SweepArgs a) {
+    typedef typename std::conditional<MIXED, float, double>::type R;
+    __shared__ uint32_t cand[kCandCap];
+    __shared__ uint16_t ring[kRing];
+    // queue: x y z and three payload columns (MODE 0: m, material; MODE 1:
+    // exp(-I^2), T, P)
+    constexpr int kTileBytes = 6 * kQueue * (int)sizeof(R);
+    __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
+                                                                                  : kRefineStageBytes];
+    R *const qx_ = reinterpret_cast<R *>(tile_buf);
+    R *const qy_ = qx_ + kQueue;
+    R *const qz_ = qy_ + kQueue;
+    R *const q1_ = qz_ + kQueue;
+    R *const q2_ = q1_ + kQueue;
+    R *const q3_ = q2_ + kQueue;
+    float *const stage = reinterpret_cast<float *>(tile_buf);
+    __shared__ V4<R> sp[kWave];   // sink: position, 1/H
+    __shared__ R smat[kWave];     // sink: material (MODE 0)
+    __shared__ double acc[4][kWave];
+
+    const int lane = threadIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    uint32_t *const stack = a.wstack + grp * kStackCap;
+    const int sid = a.grp_set[grp];
+    const SetGeom g = a.sets[sid];
+    const bool per = a.periodic != 0;
+    const int lb = 31 - __builtin_clz((unsigned)a.B);
+    const double slop = set_slop(g);
+    const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
+    const bool act = i < g.p1;
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    const double H = act ? a.Hs[i] : 0.0;
+
+    double gc[3];
+    for (int q = 0; q < 3; ++q) {
+        const double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
+        gc[q] = 0.5 * (mn + mx);
+    }
+    double gext[3];
+    for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
+    const R Lf[3] = {(R)g.L[0], (R)g.L[1], (R)g.L[2]};
+    const R hLf[3] = {(R)g.halfL[0], (R)g.halfL[1], (R)g.halfL[2]};
+    R qx, qy, qz;
+    if constexpr (MIXED) {
+        qx = (R)(per ? min_image(xi[0] - gc[0], g.L[0], g.halfL[0]) : xi[0] - gc[0]);
+        qy = (R)(per ? min_image(xi[1] - gc[1], g.L[1], g.halfL[1]) : xi[1] - gc[1]);
+        qz = (R)(per ? min_image(xi[2] - gc[2], g.L[2], g.halfL[2]) : xi[2] - gc[2]);
+    } else {
+        qx = xi[0]; qy = xi[1]; qz = xi[2];
+    }
+    const R Hr = (R)H;
+    sp[lane] = V4<R>{qx, qy, qz, act ? R(1) / Hr : R(0)};
+    if (MODE == 0) smat[lane] = (R)(act && a.mats ? a.mats[i] : 0.0);
+    for (int q = 0; q < 4; ++q) acc[q][lane] = 0.0;
+    const R H2 = MIXED ? Hr * Hr : (R)(H * H);
+    bool wrapf = MIXED && group_needs_wrap(per, g, gext, wave_max(act ? H : 0.0));
+    const GroupFilter fil = group_filter(act, xi, gc, H, per, g, gext);
+
+    Sink sk;
+    sink_bounds(act, xi, H, sk);
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
+    bool linear = false;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    int cnt = 0;
+    walk_reset(stack, ws, linear, g);
+    while (true) {
+        walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        if (ws.overflow) {
+            // restart with the linear bucket test
+            linear = true;
+            for (int q = 0; q < 4; ++q) sums[q] = 0.0;
+            walk_reset(stack, ws, true, g);
+            continue;
+        }
+        refine<false>(g, per, slop, a.nodes, xi, H, wave_max(act ? H : 0.0), act, gc, gext, cand,
+                      stage, ws);
+        const int nload = sweep_tiles(ws.ncand, a.B);
+        int qb = 0, qn = 0;
+        auto run_tile = [&](int nv) {
+            R *const tx = qx_ + qb, *const ty = qy_ + qb, *const tz = qz_ + qb;
+            R *const t1 = q1_ + qb, *const t2 = q2_ + qb, *const t3 = q3_ + qb;
+            if (lane >= nv) {
+                tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0);
+                t1[lane] = R(0); t2[lane] = R(0); t3[lane] = R(0);
+            }
+            if constexpr (!MIXED)
+                wrapf = __any(lane < nv && needs_image(per, g, gc, gext, (double)tx[lane],
+                                                       (double)ty[lane], (double)tz[lane]));
+            __syncthreads();
+            auto tile = [&](auto wrap_tag) {
+                constexpr bool WRAP = decltype(wrap_tag)::value;
+                struct PG { int s; R x, y, z, p1, p2, p3; V4<R> si; };
+                tile_pairs<1>(ring, [&](int k0, uint32_t b) {
+#pragma unroll
+                    for (int h = 0; h < 8; h += 4) {
+                        const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
+                                    Z = ld4(tz + k0 + h);
+                        R dx, dy, dz;
+                        b = push_hit(b, pair_r2<MIXED, WRAP, R>(X.x, Y.x, Z.x, qx, qy, qz, per, g,
+                                                                Lf, hLf, dx, dy, dz), H2);
+                        b = push_hit(b, pair_r2<MIXED, WRAP, R>(X.y, Y.y, Z.y, qx, qy, qz, per, g,
+                                                                Lf, hLf, dx, dy, dz), H2);
+                        b = push_hit(b, pair_r2<MIXED, WRAP, R>(X.z, Y.z, Z.z, qx, qy, qz, per, g,
+                                                                Lf, hLf, dx, dy, dz), H2);
+                        b = push_hit(b, pair_r2<MIXED, WRAP, R>(X.w, Y.w, Z.w, qx, qy, qz, per, g,
+                                                                Lf, hLf, dx, dy, dz), H2);
+                    }
+                    return b;
+                }, [&](int s, int k) {
+                    return PG{s, tx[k], ty[k], tz[k], t1[k], t2[k], t3[k], sp[s]};
+                }, [&](const PG &d, bool valid, bool) -> bool {
+                    R ex, ey, ez;
+                    const R r2 = pair_r2<MIXED, WRAP, R>(d.x, d.y, d.z, d.si.x, d.si.y, d.si.z,
+                                                         per, g, Lf, hLf, ex, ey, ez);
+                    R f, qfp;
+                    shape_f_qfp<K, R>(pair_sqrt(r2) * d.si.w, f, qfp);
+                    if (valid) {
+                        if constexpr (MODE == 0) {
+                            const R w = d.p1 * f;
+                            const R kw = d.p2 == smat[d.s] ? w : -w;
+                            atomicAdd(&acc[0][d.s], (double)w);
+                            atomicAdd(&acc[1][d.s], (double)(kw * ex));
+                            atomicAdd(&acc[2][d.s], (double)(kw * ey));
+                            atomicAdd(&acc[3][d.s], (double)(kw * ez));
+                        } else {
+                            const R w = d.p1 * f;
+                            atomicAdd(&acc[0][d.s], (double)w);
+                            atomicAdd(&acc[1][d.s], (double)(w * d.p2));
+                            atomicAdd(&acc[2][d.s], (double)(w * d.p3));
+                        }
+                    }
+                    return false;
+                }, [&](int, int, bool) -> bool { return false; }, cnt);
+            };
+            if (wrapf) tile(std::true_type{});
+            else tile(std::false_type{});
+            __syncthreads();
+            for (int q = 0; q < 4; ++q) {
+                sums[q] += acc[q][lane];
+                acc[q][lane] = 0.0;
+            }
+        };
+        for (int t = 0;;) {
+          if (t < nload) {
+            const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
+                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+            ++t;
+            R px = R(0), py = R(0), pz = R(0), p1 = R(0), p2 = R(0), p3 = R(0);
+            bool keep = false;
+            if (j >= 0) {
+                double d0 = a.xs[j] - gc[0], d1 = a.ys[j] - gc[1], d2 = a.zs[j] - gc[2];
+                if (per) {
+                    d0 = min_image(d0, g.L[0], g.halfL[0]);
+                    d1 = min_image(d1, g.L[1], g.halfL[1]);
+                    d2 = min_image(d2, g.L[2], g.halfL[2]);
+                }
+                keep = fil.inside((float)d0, (float)d1, (float)d2);
+                if constexpr (MIXED) {
+                    px = (R)d0; py = (R)d1; pz = (R)d2;
+                } else {
+                    px = a.xs[j]; py = a.ys[j]; pz = a.zs[j];
+                }
+                if constexpr (MODE == 0) {
+                    p1 = (R)a.ms[j];
+                    p2 = (R)(a.mats ? a.mats[j] : 0.0);
+                } else {
+                    const double Ij = a.imb[j];
+                    p1 = (R)exp(-Ij * Ij);
+                    p2 = (R)a.us[j];
+                    p3 = (R)a.Ps_[j];
+                }
+            }
+            const uint64_t kb = __ballot(keep);
+            if (keep) {
+                const int at = (qb + qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                               (uint32_t)(kb >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u))) &
+                               (kQueue - 1);
+                qx_[at] = px; qy_[at] = py; qz_[at] = pz;
+                q1_[at] = p1; q2_[at] = p2; q3_[at] = p3;
+            }
+            qn += __popcll(kb);
+          }
+          if (qn >= kWave || (t >= nload && qn > 0)) {
+            const int nv = qn < kWave ? qn : kWave;
+            run_tile(nv);
+            qb ^= kWave;
+            qn -= nv;
+          }
+          if (t >= nload && qn == 0) break;
+        }
+        if (ws.nstack == 0) break;
+        ws.ncand = 0;
+    }
+    if (act) {
+        if constexpr (MODE == 0) {
+            const double nrm = sqrt(sums[1] * sums[1] + sums[2] * sums[2] + sums[3] * sums[3]);
+            a.imb[i] = a.ic_alpha * nrm / (0.5 * H * sums[0]);
+        } else {
+            a.tbar[i] = sums[1] / sums[0];
+            a.pbar[i] = sums[2] / sums[0];
+        }
+    }
+}
+
 // ================================================================ neighbour lists
 
 template <bool FORCE, bool FILL>
@@ -1804,6 +2029,36 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
                                                       : forces_dispatch<false>(c, a, s);
     mark(c, E_FOR1, s);
     return e;
+}
+
+hipError_t launch_interface_sums(Ctx *c, int mode, hipStream_t s) {
+    if (c->ngroups == 0) return hipSuccess;
+    SweepArgs a = base_args(c);
+    a.mats = c->mats_has ? c->mats : nullptr;
+    a.imb = c->imbs;
+    a.us = c->us;
+    a.Ps_ = c->Ps;
+    a.tbar = c->tbar;
+    a.pbar = c->pbar;
+    a.ic_alpha = c->prm.ic_alpha;
+    dim3 grid((unsigned)c->ngroups), block(kWave);
+    const bool mixed = c->prm.precision == SPH_PREC_MIXED;
+#define GS(KK)                                                                              \
+    if (mode == 0) {                                                                        \
+        if (mixed) k_gather_sums<KK, true, 0><<<grid, block, 0, s>>>(a);                    \
+        else k_gather_sums<KK, false, 0><<<grid, block, 0, s>>>(a);                         \
+    } else {                                                                                \
+        if (mixed) k_gather_sums<KK, true, 1><<<grid, block, 0, s>>>(a);                    \
+        else k_gather_sums<KK, false, 1><<<grid, block, 0, s>>>(a);                         \
+    }
+    switch (c->prm.kernel) {
+    case 0: GS(0); break;
+    case 1: GS(1); break;
+    case 2: GS(2); break;
+    default: GS(3); break;
+    }
+#undef GS
+    return hipGetLastError();
 }
 
 hipError_t launch_neighbors(Ctx *c, int mode, int64_t *row_count_caller, const int64_t *offsets,
