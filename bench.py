@@ -77,6 +77,7 @@ def make_workload(name, small=False):
                      f"Wendland C4, 200 neighbours")
     else:
         raise ValueError(name)
+    c["workload"] = name
     c["n"] = len(c["state"]["x"])
     offs = c.get("set_offsets") or [0, c["n"]]
     c["ngroups"] = _ngroups(np.diff(offs))
@@ -88,6 +89,27 @@ WORKLOADS = ("large", "two_phase", "batch", "spheres")
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+SCHEMES = ("dynamic", "entropy", "evolved", "interface")
+
+
+def with_scheme(case, schemes):
+    """Switch on the optional schemes; the interface correction takes the
+    material ids the workload defines (the slab, the second sphere)."""
+    if not schemes:
+        return case
+    case = dict(case, params=dict(case["params"], **{k: True for k in schemes}))
+    if "interface" in schemes and "mat" not in case["state"]:
+        st = case["state"]
+        if case.get("workload") == "two_phase":
+            mat = (st["u"] < 0.5).astype(np.float64)
+        elif case.get("workload") == "spheres":
+            mat = (st["vx"] < 0.0).astype(np.float64)
+        else:
+            mat = np.zeros(len(st["x"]))
+        case["state"] = dict(st, mat=mat)
+    return case
 
 
 def run_gpu(case, precision, steps, warmup, graph=False):
@@ -156,6 +178,8 @@ def run_gpu(case, precision, steps, warmup, graph=False):
         "nr_scans_mean": st["nr_scans"] / max(1, case["ngroups"]),
         "nr_iter_max": st["nr_iter_max"], "n_noconv": st["n_noconv"],
         "n_overflow": st["n_overflow"],
+        "slots_density": st["slots_density"], "slots_force": st["slots_force"],
+        "groups_by_level": list(st["groups_by_level"]),
     }
     if tden:
         res.update({"t_density_ms": float(np.mean(tden)), "t_forces_ms": float(np.mean(tfor)),
@@ -252,6 +276,10 @@ def main():
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--workload", default="large", choices=list(WORKLOADS))
     ap.add_argument("--graph", action="store_true", help="replay one captured step as a HIP graph")
+    ap.add_argument("--bucket", type=int, default=0,
+                    help="bucket size 8, 16, 32 or 64 (default: the workload's)")
+    ap.add_argument("--scheme", default="",
+                    help="comma list of optional schemes: " + ",".join(SCHEMES))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device 5 times (calibrates the HBM "
                          "FETCH_SIZE/WRITE_SIZE counters against a known byte count)")
@@ -270,7 +298,13 @@ def main():
         print(json.dumps({"error": "the sweep runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
     log(f"generating workload {args.workload}")
-    case = make_workload(args.workload, args.small)
+    schemes = [k for k in args.scheme.split(",") if k]
+    for k in schemes:
+        if k not in SCHEMES:
+            ap.error(f"unknown scheme {k}")
+    case = with_scheme(make_workload(args.workload, args.small), schemes)
+    if args.bucket:
+        case = dict(case, params=dict(case["params"], bucket=args.bucket), autotune=False)
     graph = args.graph or case.get("graph", False)
     results = {}
     for prec in args.precisions.split(","):
@@ -318,6 +352,7 @@ def main():
                    (", mixed precision" if mixed else ", FP64") +
                    (", replayed HIP graph" if graph else ""),
                    "particles": case["n"], "bucket": head["bucket"],
+                   "schemes": schemes,
                    "parallelism": "single GPU"},
         "fp64": {k: results["fp64"].get(k) for k in ("pairs_per_s", "ms_per_step", "metric_rate",
                                                      "t_density_ms", "t_forces_ms")}
@@ -328,7 +363,8 @@ def main():
         "phases_ms": {k: head.get(k) for k in ("t_tree_ms", "t_density_ms", "t_forces_ms",
                                                "t_step_ms")},
         "pairs": {k: head[k] for k in ("pairs_density", "pairs_force", "cand_density",
-                                       "cand_force", "nr_scans_mean", "n_overflow")},
+                                       "cand_force", "nr_scans_mean", "n_overflow",
+                                       "slots_density", "slots_force", "groups_by_level")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -132,13 +132,21 @@ typedef struct {
                             over G_i and i), averages Tbar, Pbar of T = u and P with
                             weights exp(-I_j^2) W_ij(h_i), the corrected P~ and T~ and
                             rho~ = rho_EOS(T~, P~); the force pass uses rho~, P~ and the
-                            sound speed at (rho~, T~).  Not combined with SPH_FLAG_EVOLVED. */
+                            sound speed at (rho~, T~).  Not combined with SPH_FLAG_EVOLVED.
+                          SPH_FLAG_DYNAMIC: dynamic per-region bucket sizing (Sec. 2.3.2,
+                            last paragraph): the tree is built over buckets of 8 and each
+                            sink group walks it down to its own bucket size 8, 16, 32 or
+                            64, starting from `bucket` and adjusted every force pass from
+                            the group's interaction-list length (candidate particles per
+                            neighbour pair): long lists halve the buckets, short ones
+                            double them.  The level is carried by the particles from step
+                            to step.  Results do not depend on it, only the cost. */
     double ic_alpha;   /* normalisation alpha of the kernel imbalance (the paper gives no
                           value).  Default 10 (I near 1.5 at the free surface of a
                           uniform body). */
 } sph_params;
 
-enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4 };
+enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4, SPH_FLAG_DYNAMIC = 8 };
 
 /* Caller-owned device arrays, n doubles each, caller particle order.
  * State: x y z (positions inside the periodic box), vx vy vz, m, u, H (and
@@ -186,6 +194,10 @@ typedef struct {
     int32_t status;               /* device status word of the last call: SPH_OK,
                                      SPH_ERR_NOCONV or SPH_ERR_NONFINITE */
     int32_t reserved_;
+    int64_t slots_density;        /* candidate particles loaded from the interaction lists */
+    int64_t slots_force;          /* (before the per-particle filter), per pass */
+    int64_t groups_by_level[4];   /* force-pass sink groups with buckets of 8, 16, 32, 64
+                                     (SPH_FLAG_DYNAMIC; else all in the tree's size) */
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */

@@ -48,7 +48,7 @@ class Params(ctypes.Structure):
     ]
 
 
-FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE = 1, 2, 4
+FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE, FLAG_DYNAMIC = 1, 2, 4, 8
 
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H",
@@ -71,6 +71,7 @@ class Stats(ctypes.Structure):
         ("t_tree_ms", c_double), ("t_density_ms", c_double), ("t_forces_ms", c_double),
         ("t_total_ms", c_double), ("n_iter_limit", c_int64), ("n_nonfinite", c_int64),
         ("n_retest", c_int64), ("status", c_int32), ("reserved_", c_int32),
+        ("slots_density", c_int64), ("slots_force", c_int64), ("groups_by_level", c_int64 * 4),
     ]
 
 
@@ -147,7 +148,8 @@ def make_params(p: dict) -> Params:
         if name in p:
             setattr(q, name, int(p[name]))
     q.flags = ((FLAG_ENTROPY if p.get("entropy") else 0) | (FLAG_EVOLVED if p.get("evolved") else 0)
-               | (FLAG_INTERFACE if p.get("interface") else 0))
+               | (FLAG_INTERFACE if p.get("interface") else 0)
+               | (FLAG_DYNAMIC if p.get("dynamic") else 0))
     return q
 
 
@@ -282,4 +284,5 @@ class Context:
         self._check(_lib.sph_get_stats(self._h, ctypes.byref(s)))
         d = {f: getattr(s, f) for f, _ in Stats._fields_}
         d["momentum"] = tuple(s.momentum)
+        d["groups_by_level"] = tuple(s.groups_by_level)
         return d

@@ -60,6 +60,7 @@ void free_all(Ctx &c) {
     c.drec1 = c.drec2 = nullptr;
     c.rho_old = c.rho_pred = c.rho_sum = c.drs = nullptr;
     c.mats = c.imbs = c.tbar = c.pbar = nullptr;
+    c.levc = c.levs = c.d_levref = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
     if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
     if (c.h_flags) { (void)hipHostFree(c.h_flags); c.h_flags = nullptr; }
@@ -92,7 +93,7 @@ bool valid_params(const sph_params *p, std::string &why) {
     if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
         why = "stack_limit must be 0 or 2..768"; return false;
     }
-    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED | SPH_FLAG_INTERFACE)) {
+    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED | SPH_FLAG_INTERFACE | SPH_FLAG_DYNAMIC)) {
         why = "unknown flags"; return false;
     }
     if ((p->flags & SPH_FLAG_INTERFACE) && (p->flags & SPH_FLAG_EVOLVED)) {
@@ -205,6 +206,15 @@ sph_status upload_topology(sph_ctx *x, const Topology &t, hipStream_t s) {
     return SPH_OK;
 }
 
+// Dynamic bucket sizing: every particle starts at the level of the base
+// bucket size (buckets of 8 2^h).
+hipError_t reset_levels(Ctx &c, double *dst, int64_t n, hipStream_t s) {
+    const double v = (double)base_level(c.base_bucket);
+    unsigned long long bits;
+    std::memcpy(&bits, &v, sizeof(bits));
+    return launch_fill_u64(reinterpret_cast<unsigned long long *>(dst), n, bits, s);
+}
+
 // Device memory for n particles.  Every bucket-size-dependent array is sized
 // for the smallest bucket size (8), so a change of the bucket size (the
 // autotuner's trials) only rewrites the topology: after the first call at a
@@ -258,6 +268,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     if (c.prm.flags & SPH_FLAG_ENTROPY) A(c.rho_old, n);
     if (c.prm.flags & SPH_FLAG_EVOLVED) { A(c.rho_pred, n); A(c.rho_sum, n); A(c.drs, n); }
     if (c.prm.flags & SPH_FLAG_INTERFACE) { A(c.mats, n); A(c.imbs, n); A(c.tbar, n); A(c.pbar, n); }
+    if (c.dyn) { A(c.levc, n); A(c.levs, n); A(c.d_levref, 1); }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, C_NCOUNTERS);
@@ -283,6 +294,11 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     HIPCHK(x, launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s), "counters");
     HIPCHK(x, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_rep),
                               sizeof(StepReport) / 8, 0ull, s), "report");
+    if (c.dyn) {
+        HIPCHK(x, reset_levels(c, c.levc, n, s), "levels");
+        HIPCHK(x, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_levref), 1, 0ull, s),
+               "level reference");
+    }
     sph_status st = upload_topology(x, t, s);
     if (st != SPH_OK) return st;
     c.n = n;
@@ -356,6 +372,7 @@ sph_status do_density(sph_ctx *x, sph_particles *p, hipStream_t s, bool in_step 
     Ctx &c = x->c;
     Cols g = cols0();
     g.src[0] = p->H; g.dst[0] = c.Hs; g.n = 1;
+    if (c.dyn) { g.src[1] = c.levc; g.dst[1] = c.levs; g.n = 2; }
     HIPCHK(x, launch_gather(&c, g, s), "gather H");
     HIPCHK(x, launch_density(&c, s), "density");
     const bool keep_rho = in_step && (c.prm.flags & SPH_FLAG_EVOLVED);
@@ -383,16 +400,17 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
     g.src[2] = vz; g.dst[2] = c.vzs;
     g.src[3] = u; g.dst[3] = c.us;
     g.n = 4;
-    if (in_step && evolved) {
-        g.src[4] = c.rho_pred; g.dst[4] = c.rhos;
-        g.n = 5;
-    }
+    auto col = [&g](const double *src, double *dst) {
+        g.src[g.n] = src; g.dst[g.n] = dst; ++g.n;
+    };
+    if (in_step && evolved) col(c.rho_pred, c.rhos);
     if (gather_density) {
-        g.src[4] = p->H; g.dst[4] = c.Hs;
-        g.src[5] = p->rho; g.dst[5] = c.rhos;
-        g.src[6] = p->omega; g.dst[6] = c.oms;
-        g.n = 7;
+        col(p->H, c.Hs);
+        col(p->rho, c.rhos);
+        col(p->omega, c.oms);
     }
+    // (inside a step the density pass has gathered the levels)
+    if (c.dyn && !in_step) col(c.levc, c.levs);
     HIPCHK(x, launch_gather(&c, g, s), "gather force inputs");
     if (gather_density) HIPCHK(x, launch_refit(&c, s), "refit");
     const bool ic = (c.prm.flags & SPH_FLAG_INTERFACE) != 0;
@@ -421,8 +439,12 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
     o.src[4] = c.dts; o.dst[4] = p->dt;
     o.n = 5;
     if (evolved) {
-        o.src[5] = c.drs; o.dst[5] = p->drhodt;
-        o.n = 6;
+        o.src[o.n] = c.drs; o.dst[o.n] = p->drhodt;
+        o.n += 1;
+    }
+    if (c.dyn) {
+        o.src[o.n] = c.levs; o.dst[o.n] = c.levc;
+        o.n += 1;
     }
     HIPCHK(x, launch_scatter(&c, o, s), "scatter forces");
     return SPH_OK;
@@ -556,7 +578,9 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
     c.prm = *params;
     if (!(c.prm.nr_tol > 0))
         c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-5 : 1e-14;
-    c.bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    c.dyn = (c.prm.flags & SPH_FLAG_DYNAMIC) != 0;
+    c.base_bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    c.bucket = c.dyn ? 8 : c.base_bucket;   // (dynamic sizing: the tree's buckets are the finest)
     if (c.prm.stack_limit == 0) c.prm.stack_limit = kStackCap;
     c.nsets = nsets;
     if (set_offsets) c.set_off.assign(set_offsets, set_offsets + nsets + 1);
@@ -687,6 +711,11 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     HIPCHK(ctx, launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s), "counters");
     HIPCHK(ctx, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.hprev), c.n, 0ull, s),
            "H history");
+    if (c.dyn) {
+        HIPCHK(ctx, reset_levels(c, c.levc, c.n, s), "levels");
+        HIPCHK(ctx, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_levref), 1, 0ull,
+                                    s), "level reference");
+    }
     st = do_density(ctx, p, s);
     if (st != SPH_OK) return st;
     if (c.prm.flags & SPH_FLAG_ENTROPY)
@@ -785,6 +814,9 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->n_nonfinite = (int64_t)c.h_cnt[C_NONFINITE];
     out->n_retest = (int64_t)c.h_cnt[C_RETEST];
     out->status = (int32_t)flags_status(&c.h_cnt[C_ITERLIM]);
+    out->slots_density = (int64_t)c.h_cnt[C_SLOTS_D];
+    out->slots_force = (int64_t)c.h_cnt[C_SLOTS_F];
+    for (int q = 0; q < 4; ++q) out->groups_by_level[q] = (int64_t)c.h_cnt[C_LEV0 + q];
     c.status_pending = false;   // reported here, not again by the next call
     auto span = [&](int a, int b) -> double {
         if (!((c.ev_mask >> a) & 1u) || !((c.ev_mask >> b) & 1u)) return -1.0;
@@ -822,7 +854,7 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     if (st != SPH_OK) return st;
     st = take_status(ctx);
     if (st != SPH_OK) return st;
-    if (n == 0) { *bucket = c.bucket; return SPH_OK; }
+    if (n == 0) { *bucket = c.dyn ? c.base_bucket : c.bucket; return SPH_OK; }
     // every trial starts from the same first guess of H (kept in the context's
     // scratch column, so the trials allocate nothing)
     st = setup(ctx, n, s);
@@ -832,10 +864,13 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     const bool timing = c.timing;
     st = sph_set_timing(ctx, 1);
     const int cands[4] = {8, 16, 32, 64};
-    int best = c.bucket;
+    int best = c.dyn ? c.base_bucket : c.bucket;
     double tbest = 1e300;
     for (int q = 0; q < 4 && st == SPH_OK && e == hipSuccess; ++q) {
-        c.bucket = cands[q];
+        // (dynamic sizing: the tree keeps buckets of 8; the trials set the
+        // level the groups start from)
+        if (c.dyn) c.base_bucket = cands[q];
+        else c.bucket = cands[q];
         double t = 1e300;
         for (int rep = 0; rep < 2 && st == SPH_OK && e == hipSuccess; ++rep) {
             e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
@@ -849,7 +884,8 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
         if (t < tbest) { tbest = t; best = cands[q]; }
     }
     if (st == SPH_OK && e == hipSuccess) {
-        c.bucket = best;
+        if (c.dyn) c.base_bucket = best;
+        else c.bucket = best;
         e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) st = sph_init(ctx, p, n, stream);
     }
@@ -884,7 +920,9 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     c.prm = *params;
     if (!(c.prm.nr_tol > 0)) c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-5 : 1e-14;
     if (c.prm.stack_limit == 0) c.prm.stack_limit = kStackCap;
-    c.bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    c.dyn = (c.prm.flags & SPH_FLAG_DYNAMIC) != 0;
+    c.base_bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
+    c.bucket = c.dyn ? 8 : c.base_bucket;
     c.nsets = 1;
     c.timing = false;
     c.capturing = false;
@@ -946,6 +984,8 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     c.drs = nullptr;
     if (c.prm.flags & SPH_FLAG_EVOLVED) cv.take(&c.drs, n);
     c.mats = c.imbs = c.tbar = c.pbar = nullptr;
+    c.levc = c.levs = c.d_levref = nullptr;
+    if (c.dyn) { cv.take(&c.levc, n); cv.take(&c.levs, n); cv.take(&c.d_levref, 1); }
     if (c.prm.flags & SPH_FLAG_INTERFACE) {
         cv.take(&c.mats, n); cv.take(&c.imbs, n); cv.take(&c.tbar, n); cv.take(&c.pbar, n);
     }
@@ -960,6 +1000,10 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     if (hipGetLastError() != hipSuccess) return SPH_ERR_HIP;
     if (launch_init_nodes(&c, s) != hipSuccess) return SPH_ERR_HIP;
     if (launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s) != hipSuccess) return SPH_ERR_HIP;
+    if (c.dyn && (reset_levels(c, c.levc, n, s) != hipSuccess ||
+                  launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_levref), 1, 0ull, s) !=
+                      hipSuccess))
+        return SPH_ERR_HIP;
     if (launch_tree_build(&c, p, s) != hipSuccess) return SPH_ERR_HIP;
     sph_status st = do_density(x, p, s);
     if (st != SPH_OK) return st;

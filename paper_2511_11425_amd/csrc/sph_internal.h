@@ -26,11 +26,20 @@ enum Counter {
     C_NOCONV, C_REWALK, C_OVERFLOW, C_ROWLONG,
     C_ITERLIM, C_NONFINITE,               // the status word (adjacent: copied together)
     C_RETEST,                             // mixed pairs re-tested in FP64 (exact membership)
+    C_SLOTS_D, C_SLOTS_F,                 // candidate slots loaded (interaction-list lengths)
+    C_LEV0, C_LEV1, C_LEV2, C_LEV3,       // force-pass sink groups per bucket level
     C_NTRANSIENT,                         // counters above are cleared by every call
     C_PAIRS_D_TOT = C_NTRANSIENT,         // running totals since the context was made
     C_PAIRS_F_TOT,
     C_NCOUNTERS
 };
+
+// Dynamic bucket sizing: level h of a bucket size (buckets of 8 2^h, h <= 3).
+inline int base_level(int bucket) {
+    int h = 0;
+    while ((8 << h) < bucket && h < 3) ++h;
+    return h;
+}
 
 // Timing events recorded around the phases when timing is on.
 enum TimingEvent { E_BEGIN = 0, E_TREE0, E_TREE1, E_DEN0, E_DEN1, E_FOR0, E_FOR1, E_END, E_NEVENTS };
@@ -122,6 +131,15 @@ struct Ctx {
     double *drs = nullptr;     // sorted: continuity rate of the force pass (evolved density)
     // interface correction (sorted): material ids, imbalance, averages
     double *mats = nullptr, *imbs = nullptr, *tbar = nullptr, *pbar = nullptr;
+    // dynamic bucket sizing: the tree is built over buckets of 8; each group's
+    // level h (buckets of 8 2^h) follows its list lengths from step to step
+    bool dyn = false;
+    int32_t base_bucket = 32;  // bucket size the levels start from
+    double *levc = nullptr;    // caller order: level of each particle's group
+    double *levs = nullptr;    // sorted
+    double *d_levref = nullptr;// mean list length per pair of the last force pass (one value;
+                               // kept off the counters' cache line, which the sweeps' atomics
+                               // keep busy)
     bool mats_has = false;     // the caller gave material ids
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 

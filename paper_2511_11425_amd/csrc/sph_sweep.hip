@@ -524,7 +524,11 @@ struct SweepArgs {
     double ic_alpha;
     int entropy;            // du/dt without the PdV term (entropy-conserving update)
     unsigned long long *cnt;
-    int B;
+    int B;                  // bucket size of the tree (the finest with dynamic sizing)
+    const double *levs;     // dynamic bucket sizing: per sorted particle, the level h of
+    double *levs_out;       //   its group (buckets of B 2^h); null when off
+    int lev_max;            //   largest level (B 2^lev_max <= 64)
+    const double *lev_ref;  //   mean list length per pair of the previous force pass
     int periodic;
     double oversel, tol, h_max, n_ngb;
     int maxit;
@@ -544,6 +548,32 @@ __device__ __forceinline__ double set_hcap(const SetGeom &g, bool per, double h_
     if (!per) return h_max;
     double lm = fmin(g.L[0], fmin(g.L[1], g.L[2]));
     return fmin(h_max, 0.5 * lm);
+}
+
+// Dynamic bucket sizing (Sec. 2.3.2, last paragraph).  The tree is built
+// over buckets of B particles (the finest size); a group at level h walks it
+// only down to the nodes of height h, which are contiguous runs of B 2^h
+// particles, and treats those as its buckets.  The copy of the set's
+// geometry is adjusted to that level (leaf count, bucket count, depth) and
+// the group's bucket size returned.  A group's level is the smallest level
+// any of its particles carries from the previous step (the most refined
+// wins), so a region whose lists blew up keeps small buckets after the
+// particles are re-sorted.
+__device__ __forceinline__ int group_bucket(const SweepArgs &a, SetGeom &g, int64_t i0, bool act,
+                                            int &level) {
+    int B = a.B;
+    level = 0;
+    if (!a.levs) return B;
+    const int lane = threadIdx.x;
+    int h = (int)wave_min(act ? a.levs[i0 + lane] : 1e30);
+    h = h < 0 ? 0 : h;
+    h = h > a.lev_max ? a.lev_max : h;
+    h = h > g.depth ? g.depth : h;
+    level = h;
+    g.nbp >>= h;
+    g.nb = (g.nb + (1 << h) - 1) >> h;
+    g.depth -= h;
+    return B << h;
 }
 
 // Stage 64 candidate slots starting at candidate-list position t0 (64/B
@@ -913,14 +943,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
-    const SetGeom g = a.sets[sid];
+    SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
-    const int lb = 31 - __builtin_clz((unsigned)a.B);   // B = 2^lb
     const double slop = set_slop(g);
     const double cap = set_hcap(g, per, a.h_max);
     const int64_t i0 = g.p0 + (grp - g.g0) * kGroup;   // the group's first sink
     const int64_t i = i0 + lane;
     const bool act = i < g.p1;
+    int level;
+    const int Bg = group_bucket(a, g, i0, act, level);   // this group's bucket size
+    const int lb = 31 - __builtin_clz((unsigned)Bg);     // Bg = 2^lb
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double mi = act ? a.ms[i] : 0.0;
     double H = act ? a.Hs[i] : 0.0;
@@ -971,6 +1003,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     int scans = 0, rewalks = 0;
     int retests = 0;   // pairs the wave re-tested in FP64 (mixed)
     unsigned long long cand_tested = 0;
+    unsigned long long slots = 0;   // candidate slots loaded (before the filter)
     bool need_walk = true;
 
     while (true) {
@@ -1029,7 +1062,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                 refine<false>(g, per, slop, a.nodes, xi, Hw, wave_max(act ? Hw : 0.0), act, gc, gext, cand,
                           stage, ws);
             }
-            const int nload = sweep_tiles(ws.ncand, a.B);
+            const int nload = sweep_tiles(ws.ncand, Bg);
             if constexpr (MIXED) {
                 // (after the refinement, which shares this LDS)
                 sH[lane] = H;
@@ -1120,9 +1153,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
             for (int t = 0;;) {
               if (t < nload) {
                 const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
-                                                     : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+                                                     : slot_index(g, cand, ws.ncand, t << (6 - lb), Bg);
                 const Slot cur = j >= 0 ? Slot{j, a.xs[j], a.ys[j], a.zs[j], a.ms[j]}
                                         : Slot{-1, 0.0, 0.0, 0.0, 0.0};
+                slots += (unsigned long long)__popcll(__ballot(j >= 0));
                 ++t;
                 R px = R(0), py = R(0), pz = R(0), pm = R(0);
                 bool keep = false;
@@ -1246,6 +1280,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
         if (nlim) atomicAdd(&a.cnt[C_ITERLIM], (unsigned long long)nlim);
         if (nnan) atomicAdd(&a.cnt[C_NONFINITE], (unsigned long long)nnan);
         if (nret) atomicAdd(&a.cnt[C_RETEST], (unsigned long long)nret);
+        atomicAdd(&a.cnt[C_SLOTS_D], slots);
         atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_PAIRS_D_TOT], (unsigned long long)pairs_n);
         atomicAdd(&a.cnt[C_CAND_D], cand_tested * (unsigned long long)nact);
@@ -1303,13 +1338,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
-    const SetGeom g = a.sets[sid];
+    SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
-    const int lb = 31 - __builtin_clz((unsigned)a.B);   // B = 2^lb
     const double slop = set_slop(g);
     const int64_t i0 = g.p0 + (grp - g.g0) * kGroup;   // the group's first sink
     const int64_t i = i0 + lane;
     const bool act = i < g.p1;
+    int level;
+    const int Bg = group_bucket(a, g, i0, act, level);   // this group's bucket size
+    const int lb = 31 - __builtin_clz((unsigned)Bg);     // Bg = 2^lb
+    const double lref = a.levs_out ? *a.lev_ref : 0.0;    // (for the level rule at the end)
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double Hd = act ? a.Hs[i] : 0.0;
     const R sig = (R)sigma_of<K>();
@@ -1376,6 +1414,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     int rej = 0;       // accepted pairs that the FP64 re-test rejected (wave total)
     int retests = 0;   // pairs the wave re-tested in FP64
     unsigned long long cand_tested = 0;
+    unsigned long long slots = 0;   // candidate slots loaded (before the filter)
     walk_reset(stack, ws, linear, g);
 
     while (true) {
@@ -1389,12 +1428,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
             rej = 0;
             retests = 0;
             cand_tested = 0;
+            slots = 0;
             amu[lane] = 0;
             walk_reset(stack, ws, true, g);
             continue;
         }
         refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
-        const int nload = sweep_tiles(ws.ncand, a.B);
+        const int nload = sweep_tiles(ws.ncand, Bg);
         int qb = 0, qn = 0;   // candidate queue: first entry, entries
         // One tile: the 64 queue entries from qb (nv of them valid).
         auto run_tile = [&](int nv) {
@@ -1541,7 +1581,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         // the next load's slot is fetched while this one is filtered
         auto load_slot = [&](int t) -> Slot {
             const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
-                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), Bg);
             if (j < 0) return Slot{-1, 0.0, 0.0, 0.0, 0.0};
             return Slot{j, a.xs[j], a.ys[j], a.zs[j], a.Hs[j]};
         };
@@ -1550,6 +1590,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
           if (t < nload) {
             const Slot cur = nxt;
             const int64_t j = cur.j;
+            slots += (unsigned long long)__popcll(__ballot(j >= 0));
             ++t;
             if (t < nload) nxt = load_slot(t);
             R px = R(0), py = R(0), pz = R(0), ph2 = R(0);
@@ -1620,7 +1661,23 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     int nact = wave_sum_i(act ? 1 : 0);
     const int nnan = wave_sum_i(nonfinite ? 1 : 0);
     const int nret = retests;   // (a wave total)
+    if (a.levs_out) {
+        // next step's level from this pass's list length r (candidate slots
+        // loaded per neighbour pair of an average sink), against the mean r
+        // of the previous force pass: a list more than 1.5 times as long as
+        // the mean halves the group's buckets, one shorter than the mean
+        // doubles them again, up to the base size (the first pass keeps the
+        // levels)
+        const double pps = nact > 0 ? (double)pairs_n / nact : 0.0;
+        const double r = (double)slots / (pps > 1.0 ? pps : 1.0);
+        int hn = level;
+        if (lref > 0.0) hn += r > 1.5 * lref ? -1 : (r < lref ? 1 : 0);
+        hn = hn < 0 ? 0 : (hn > a.lev_max ? a.lev_max : hn);
+        if (act) a.levs_out[i] = (double)hn;
+    }
     if (lane == 0) {
+        atomicAdd(&a.cnt[C_SLOTS_F], slots);
+        atomicAdd(&a.cnt[C_LEV0 + level], 1ull);
         if (nnan) atomicAdd(&a.cnt[C_NONFINITE], (unsigned long long)nnan);
         if (nret) atomicAdd(&a.cnt[C_RETEST], (unsigned long long)nret);
         atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs_n);
@@ -1667,12 +1724,14 @@ __global__ __launch_bounds__(kWave) void k_gather_sums(SweepArgs a) {
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
-    const SetGeom g = a.sets[sid];
+    SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
-    const int lb = 31 - __builtin_clz((unsigned)a.B);
     const double slop = set_slop(g);
     const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
     const bool act = i < g.p1;
+    int level;
+    const int Bg = group_bucket(a, g, g.p0 + (grp - g.g0) * kGroup, act, level);
+    const int lb = 31 - __builtin_clz((unsigned)Bg);
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double H = act ? a.Hs[i] : 0.0;
 
@@ -1719,7 +1778,7 @@ __global__ __launch_bounds__(kWave) void k_gather_sums(SweepArgs a) {
         }
         refine<false>(g, per, slop, a.nodes, xi, H, wave_max(act ? H : 0.0), act, gc, gext, cand,
                       stage, ws);
-        const int nload = sweep_tiles(ws.ncand, a.B);
+        const int nload = sweep_tiles(ws.ncand, Bg);
         int qb = 0, qn = 0;
         auto run_tile = [&](int nv) {
             R *const tx = qx_ + qb, *const ty = qy_ + qb, *const tz = qz_ + qb;
@@ -1788,7 +1847,7 @@ __global__ __launch_bounds__(kWave) void k_gather_sums(SweepArgs a) {
         for (int t = 0;;) {
           if (t < nload) {
             const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
-                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), a.B);
+                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), Bg);
             ++t;
             R px = R(0), py = R(0), pz = R(0), p1 = R(0), p2 = R(0), p3 = R(0);
             bool keep = false;
@@ -1970,6 +2029,10 @@ inline SweepArgs base_args(Ctx *c) {
     a.wstack = c->d_wstack;
     a.cnt = c->d_cnt;
     a.B = c->bucket;
+    a.levs = c->dyn ? c->levs : nullptr;
+    a.levs_out = c->dyn ? c->levs : nullptr;
+    a.lev_max = c->dyn ? base_level(c->base_bucket) : 0;
+    a.lev_ref = c->d_levref;
     a.periodic = c->prm.periodic;
     a.oversel = c->prm.oversel;
     a.tol = c->prm.nr_tol;
@@ -2018,6 +2081,15 @@ hipError_t launch_density(Ctx *c, hipStream_t s) {
     return e;
 }
 
+// Mean list length per pair of the force pass just run (the reference of the
+// next pass's level rule): slots per group over pairs per particle.
+__global__ void k_level_ref(const unsigned long long *cnt, int64_t ngroups, int64_t n,
+                            double *ref) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double pps = (double)cnt[C_PAIRS_F] / (double)(n > 0 ? n : 1);
+    *ref = (double)cnt[C_SLOTS_F] / (double)(ngroups > 0 ? ngroups : 1) / (pps > 1.0 ? pps : 1.0);
+}
+
 hipError_t launch_forces(Ctx *c, hipStream_t s) {
     if (c->ngroups == 0) return hipSuccess;
     SweepArgs a = base_args(c);
@@ -2028,6 +2100,10 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
     hipError_t e = c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
                                                       : forces_dispatch<false>(c, a, s);
     mark(c, E_FOR1, s);
+    if (e == hipSuccess && c->dyn) {
+        k_level_ref<<<1, 64, 0, s>>>(c->d_cnt, c->ngroups, c->n, c->d_levref);
+        e = hipGetLastError();
+    }
     return e;
 }
 
