@@ -271,7 +271,8 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     if (c.dyn) { A(c.levc, n); A(c.levs, n); A(c.d_levref, 1); }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
-    A(c.d_cnt, C_NCOUNTERS);
+    A(c.d_cnt, kCntShards * kCntStride);
+    A(c.d_csum, C_NCOUNTERS);
     A(c.d_rep, 1);
     A(c.d_dt, ns);
     A(c.d_set_dtnext, ns);
@@ -291,7 +292,8 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     c.h_flags[0] = c.h_flags[1] = 0;
     if (!c.status_ev)
         HIPCHK(x, hipEventCreateWithFlags(&c.status_ev, hipEventDisableTiming), "status event");
-    HIPCHK(x, launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s), "counters");
+    HIPCHK(x, launch_fill_u64(c.d_cnt, kCntShards * kCntStride, 0ull, s), "counters");
+    HIPCHK(x, launch_fill_u64(c.d_csum, C_NCOUNTERS, 0ull, s), "counter sums");
     HIPCHK(x, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_rep),
                               sizeof(StepReport) / 8, 0ull, s), "report");
     if (c.dyn) {
@@ -345,8 +347,13 @@ sph_status take_status(sph_ctx *x) {
 // call's work, followed by the status event (skipped while capturing a graph;
 // sph_graph_launch posts it after the replay).
 hipError_t post_status(Ctx &c, hipStream_t s) {
+    if (c.d_cnt) {
+        // (the sums the host reads: also inside a captured graph)
+        hipError_t e = launch_fold_counters(&c, s);
+        if (e != hipSuccess) return e;
+    }
     if (c.capturing || !c.h_flags || !c.status_ev) return hipSuccess;
-    hipError_t e = hipMemcpyAsync(c.h_flags, c.d_cnt + C_ITERLIM, 2 * sizeof(unsigned long long),
+    hipError_t e = hipMemcpyAsync(c.h_flags, c.d_csum + C_ITERLIM, 2 * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(c.status_ev, s);
     if (e == hipSuccess) c.status_pending = true;
@@ -356,7 +363,7 @@ hipError_t post_status(Ctx &c, hipStream_t s) {
 hipError_t reset_counters(Ctx &c, hipStream_t s) {
     c.ev_mask = 0;
     mark(&c, E_BEGIN, s);
-    return launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s);
+    return launch_reset_counters(&c, C_NTRANSIENT, s);
 }
 
 Cols cols0() {
@@ -655,7 +662,8 @@ sph_status sph_neighbors(sph_ctx *ctx, const sph_particles *p, int32_t mode, int
         HIPCHK(ctx, launch_neighbors(&c, mode, nullptr, offsets, idx, s), "fill");
         HIPCHK(ctx, launch_sort_rows(&c, offsets, idx, s), "sort rows");
     }
-    HIPCHK(ctx, hipMemcpyAsync(c.h_cnt, c.d_cnt, sizeof(unsigned long long) * C_NCOUNTERS,
+    HIPCHK(ctx, launch_fold_counters(&c, s), "fold counters");
+    HIPCHK(ctx, hipMemcpyAsync(c.h_cnt, c.d_csum, sizeof(unsigned long long) * C_NCOUNTERS,
                                hipMemcpyDeviceToHost, s), "counters");
     HIPCHK(ctx, hipStreamSynchronize(s), "sync");
     if (c.h_cnt[C_ROWLONG]) return fail(ctx, SPH_ERR_CAPACITY, "a row exceeds 4096 entries");
@@ -708,7 +716,7 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
     if (st != SPH_OK) return st;
     st = sph_build_tree(ctx, p, n, stream);   // (takes the previous status)
     if (st != SPH_OK) return st;
-    HIPCHK(ctx, launch_fill_u64(c.d_cnt, C_NTRANSIENT, 0ull, s), "counters");
+    HIPCHK(ctx, launch_reset_counters(&c, C_NTRANSIENT, s), "counters");
     HIPCHK(ctx, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.hprev), c.n, 0ull, s),
            "H history");
     if (c.dyn) {
@@ -791,7 +799,7 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->n = c.n;
     if (!c.d_cnt) return SPH_OK;
     HIPCHK(ctx, hipStreamSynchronize(c.last_stream), "sync");
-    HIPCHK(ctx, hipMemcpy(c.h_cnt, c.d_cnt, sizeof(unsigned long long) * C_NCOUNTERS,
+    HIPCHK(ctx, hipMemcpy(c.h_cnt, c.d_csum, sizeof(unsigned long long) * C_NCOUNTERS,
                           hipMemcpyDeviceToHost), "counters");
     HIPCHK(ctx, hipMemcpy(c.h_rep, c.d_rep, sizeof(StepReport), hipMemcpyDeviceToHost), "report");
     out->pairs_density = (int64_t)c.h_cnt[C_PAIRS_D];
@@ -991,7 +999,8 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     }
     cv.take(&c.d_wstack, (size_t)c.ngroups * kStackCap);
     cv.take(&c.d_scan_tmp, c.scan_tmp_len);
-    cv.take(&c.d_cnt, C_NCOUNTERS);
+    cv.take(&c.d_cnt, kCntShards * kCntStride);
+    cv.take(&c.d_csum, C_NCOUNTERS);
     if (!cv.ok) return SPH_ERR_CAPACITY;
 
     const int64_t nt = std::max<int64_t>(std::max<int64_t>(c.ngroups, nb), depth + 1);
@@ -999,7 +1008,9 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
         c.d_sets, c.d_grp_set, c.ngroups, c.d_bkt_set, nb, pref, depth, g);
     if (hipGetLastError() != hipSuccess) return SPH_ERR_HIP;
     if (launch_init_nodes(&c, s) != hipSuccess) return SPH_ERR_HIP;
-    if (launch_fill_u64(c.d_cnt, C_NCOUNTERS, 0ull, s) != hipSuccess) return SPH_ERR_HIP;
+    if (launch_fill_u64(c.d_cnt, kCntShards * kCntStride, 0ull, s) != hipSuccess ||
+        launch_fill_u64(c.d_csum, C_NCOUNTERS, 0ull, s) != hipSuccess)
+        return SPH_ERR_HIP;
     if (c.dyn && (reset_levels(c, c.levc, n, s) != hipSuccess ||
                   launch_fill_u64(reinterpret_cast<unsigned long long *>(c.d_levref), 1, 0ull, s) !=
                       hipSuccess))

@@ -41,6 +41,17 @@ inline int base_level(int bucket) {
     return h;
 }
 
+// The counters are accumulated in kCntShards copies, each on a 256-byte line
+// of its own (sink group g adds to copy g mod kCntShards): the sweeps end
+// every wave with a handful of 64-bit atomics, which on a single line
+// serialise in the L2 and hold the finishing waves back (measured: a third
+// of the density pass at 2M particles).  A fold kernel sums the copies into
+// the summary block the host reads (maximum for C_NR_ITER_MAX).
+constexpr int kCntShards = 16;
+constexpr int kCntStride = 32;   // 64-bit counters per copy
+static_assert(C_NCOUNTERS <= kCntStride, "counter copy too small");
+__host__ __device__ inline int64_t cnt_shard(int64_t g) { return (g % kCntShards) * kCntStride; }
+
 // Timing events recorded around the phases when timing is on.
 enum TimingEvent { E_BEGIN = 0, E_TREE0, E_TREE1, E_DEN0, E_DEN1, E_FOR0, E_FOR1, E_END, E_NEVENTS };
 
@@ -148,7 +159,8 @@ struct Ctx {
     int64_t scan_tmp_len = 0;
 
     // counters, step report, reduction partials
-    unsigned long long *d_cnt = nullptr;
+    unsigned long long *d_cnt = nullptr;    // kCntShards copies of the counters
+    unsigned long long *d_csum = nullptr;   // their sums (C_NCOUNTERS), what the host reads
     StepReport *d_rep = nullptr;
     double *d_dt = nullptr;         // per set: step size used by the kick kernels
     double *d_set_dtnext = nullptr; // per set: min_i dt_i of the last force pass
@@ -201,6 +213,9 @@ struct Cols {
     int n;
 };
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+// zero counters [0, last) of every copy; fold the copies into d_csum
+hipError_t launch_reset_counters(Ctx *c, int last, hipStream_t s);
+hipError_t launch_fold_counters(Ctx *c, hipStream_t s);
 hipError_t launch_gather(Ctx *c, const Cols &cols, hipStream_t s);   // dst[k] = src[perm[k]]
 hipError_t launch_scatter(Ctx *c, const Cols &cols, hipStream_t s);  // dst[perm[k]] = src[k]
 hipError_t launch_eos(Ctx *c, const double *u_sorted, double *P_caller, double *c_caller,

@@ -31,6 +31,23 @@ __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
     if (i < n) p[i] = v;
 }
 
+__global__ void k_reset_counters(unsigned long long *cnt, int last) {
+    const int t = threadIdx.x;
+    if (t < kCntShards * kCntStride && t % kCntStride < last) cnt[t] = 0ull;
+}
+
+__global__ void k_fold_counters(const unsigned long long *__restrict__ cnt,
+                                unsigned long long *__restrict__ sum) {
+    const int k = threadIdx.x;
+    if (k >= C_NCOUNTERS) return;
+    unsigned long long v = 0;
+    for (int q = 0; q < kCntShards; ++q) {
+        const unsigned long long w = cnt[q * kCntStride + k];
+        v = k == C_NR_ITER_MAX ? (w > v ? w : v) : v + w;
+    }
+    sum[k] = v;
+}
+
 __global__ void k_gather_cols(const uint32_t *__restrict__ perm, int64_t n, Cols c) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -376,6 +393,16 @@ int reduce_partials() { return kRedBlocks; }
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_fill_u64<<<nblk(n, kThreads), kThreads, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counters(Ctx *c, int last, hipStream_t s) {
+    k_reset_counters<<<1, kCntShards * kCntStride, 0, s>>>(c->d_cnt, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_counters(Ctx *c, hipStream_t s) {
+    k_fold_counters<<<1, kCntStride, 0, s>>>(c->d_cnt, c->d_csum);
     return hipGetLastError();
 }
 

@@ -941,6 +941,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 
     const int lane = threadIdx.x;
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    unsigned long long *const ctr = a.cnt + cnt_shard(grp);   // this group's counter copy
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
     SetGeom g = a.sets[sid];
@@ -1277,18 +1278,18 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const int nnan = wave_sum_i(nonfinite ? 1 : 0);
     const int nret = retests;   // (a wave total)
     if (lane == 0) {
-        if (nlim) atomicAdd(&a.cnt[C_ITERLIM], (unsigned long long)nlim);
-        if (nnan) atomicAdd(&a.cnt[C_NONFINITE], (unsigned long long)nnan);
-        if (nret) atomicAdd(&a.cnt[C_RETEST], (unsigned long long)nret);
-        atomicAdd(&a.cnt[C_SLOTS_D], slots);
-        atomicAdd(&a.cnt[C_PAIRS_D], (unsigned long long)pairs_n);
-        atomicAdd(&a.cnt[C_PAIRS_D_TOT], (unsigned long long)pairs_n);
-        atomicAdd(&a.cnt[C_CAND_D], cand_tested * (unsigned long long)nact);
-        atomicMax(&a.cnt[C_NR_ITER_MAX], (unsigned long long)scans);
-        atomicAdd(&a.cnt[C_NR_SCANS], (unsigned long long)scans);
-        if (bad) atomicAdd(&a.cnt[C_NOCONV], (unsigned long long)bad);
-        if (rewalks) atomicAdd(&a.cnt[C_REWALK], (unsigned long long)rewalks);
-        if (overflows) atomicAdd(&a.cnt[C_OVERFLOW], (unsigned long long)overflows);
+        if (nlim) atomicAdd(&ctr[C_ITERLIM], (unsigned long long)nlim);
+        if (nnan) atomicAdd(&ctr[C_NONFINITE], (unsigned long long)nnan);
+        if (nret) atomicAdd(&ctr[C_RETEST], (unsigned long long)nret);
+        atomicAdd(&ctr[C_SLOTS_D], slots);
+        atomicAdd(&ctr[C_PAIRS_D], (unsigned long long)pairs_n);
+        atomicAdd(&ctr[C_PAIRS_D_TOT], (unsigned long long)pairs_n);
+        atomicAdd(&ctr[C_CAND_D], cand_tested * (unsigned long long)nact);
+        atomicMax(&ctr[C_NR_ITER_MAX], (unsigned long long)scans);
+        atomicAdd(&ctr[C_NR_SCANS], (unsigned long long)scans);
+        if (bad) atomicAdd(&ctr[C_NOCONV], (unsigned long long)bad);
+        if (rewalks) atomicAdd(&ctr[C_REWALK], (unsigned long long)rewalks);
+        if (overflows) atomicAdd(&ctr[C_OVERFLOW], (unsigned long long)overflows);
     }
 }
 
@@ -1336,6 +1337,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
 
     const int lane = threadIdx.x;
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    unsigned long long *const ctr = a.cnt + cnt_shard(grp);   // this group's counter copy
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
     SetGeom g = a.sets[sid];
@@ -1676,14 +1678,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         if (act) a.levs_out[i] = (double)hn;
     }
     if (lane == 0) {
-        atomicAdd(&a.cnt[C_SLOTS_F], slots);
-        atomicAdd(&a.cnt[C_LEV0 + level], 1ull);
-        if (nnan) atomicAdd(&a.cnt[C_NONFINITE], (unsigned long long)nnan);
-        if (nret) atomicAdd(&a.cnt[C_RETEST], (unsigned long long)nret);
-        atomicAdd(&a.cnt[C_PAIRS_F], (unsigned long long)pairs_n);
-        atomicAdd(&a.cnt[C_PAIRS_F_TOT], (unsigned long long)pairs_n);
-        atomicAdd(&a.cnt[C_CAND_F], cand_tested * (unsigned long long)nact);
-        if (overflows) atomicAdd(&a.cnt[C_OVERFLOW], (unsigned long long)overflows);
+        atomicAdd(&ctr[C_SLOTS_F], slots);
+        atomicAdd(&ctr[C_LEV0 + level], 1ull);
+        if (nnan) atomicAdd(&ctr[C_NONFINITE], (unsigned long long)nnan);
+        if (nret) atomicAdd(&ctr[C_RETEST], (unsigned long long)nret);
+        atomicAdd(&ctr[C_PAIRS_F], (unsigned long long)pairs_n);
+        atomicAdd(&ctr[C_PAIRS_F_TOT], (unsigned long long)pairs_n);
+        atomicAdd(&ctr[C_CAND_F], cand_tested * (unsigned long long)nact);
+        if (overflows) atomicAdd(&ctr[C_OVERFLOW], (unsigned long long)overflows);
     }
 }
 
@@ -1918,6 +1920,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
 
     const int lane = threadIdx.x;
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    unsigned long long *const ctr = a.cnt + cnt_shard(grp);   // this group's counter copy
     const int sid = a.grp_set[grp];
     const SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
@@ -1977,7 +1980,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(SweepArgs a) {
         ws.ncand = 0;
     }
     if (!FILL && act) a.row_count[orig] = cnt;
-    if (lane == 0 && overflows) atomicAdd(&a.cnt[C_OVERFLOW], (unsigned long long)overflows);
+    if (lane == 0 && overflows) atomicAdd(&ctr[C_OVERFLOW], (unsigned long long)overflows);
 }
 
 // One workgroup per row: bitonic sort in LDS (rows up to kMaxRow entries).
@@ -1990,7 +1993,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
     const int64_t len = e - b;
     if (len <= 1) return;
     if (len > kMaxRow) {
-        if (threadIdx.x == 0) atomicAdd(&cnt[C_ROWLONG], 1ull);
+        if (threadIdx.x == 0) atomicAdd(&cnt[cnt_shard(blockIdx.x) + C_ROWLONG], 1ull);
         return;
     }
     int P = 1;
@@ -2086,8 +2089,13 @@ hipError_t launch_density(Ctx *c, hipStream_t s) {
 __global__ void k_level_ref(const unsigned long long *cnt, int64_t ngroups, int64_t n,
                             double *ref) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double pps = (double)cnt[C_PAIRS_F] / (double)(n > 0 ? n : 1);
-    *ref = (double)cnt[C_SLOTS_F] / (double)(ngroups > 0 ? ngroups : 1) / (pps > 1.0 ? pps : 1.0);
+    unsigned long long pairs = 0, slots = 0;
+    for (int q = 0; q < kCntShards; ++q) {
+        pairs += cnt[q * kCntStride + C_PAIRS_F];
+        slots += cnt[q * kCntStride + C_SLOTS_F];
+    }
+    const double pps = (double)pairs / (double)(n > 0 ? n : 1);
+    *ref = (double)slots / (double)(ngroups > 0 ? ngroups : 1) / (pps > 1.0 ? pps : 1.0);
 }
 
 hipError_t launch_forces(Ctx *c, hipStream_t s) {
