@@ -23,6 +23,7 @@ which is "parity unpinned" (the paper quotes only whole-run energy errors).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from ctypes import c_double, c_int, c_int32, c_int64, POINTER
@@ -498,3 +499,134 @@ def reductions(s: dict) -> dict:
     ek = float(np.sum(0.5 * m * (s["vx"] ** 2 + s["vy"] ** 2 + s["vz"] ** 2)))
     ei = float(np.sum(m * s["u"]))
     return {"momentum": (px, py, pz), "e_kin": ek, "e_int": ei, "e_tot": ek + ei}
+
+
+# ---- individual time steps (Sec. 2.3.6) ---------------------------------------
+#
+# Every particle steps with a power-of-two fraction 2^-r of the base step dt0
+# (dt_max); r is its rung, 0 <= r <= rung_max.  Time is counted in units of
+# the finest step dt0 2^-rung_max, so a particle on rung r has a step of
+# L = 2^(rung_max - r) units and its steps start at multiples of L.  A
+# substep runs from the current time T to the next step boundary of any
+# particle.  State between substeps: particles at a step boundary (T a
+# multiple of their L) hold v, u at T; the others hold their half-step
+# values.
+
+def step_units(params: dict, rung):
+    R = int(params.get("rung_max", 8))
+    return np.left_shift(np.int64(1), (R - np.asarray(rung, dtype=np.int64)))
+
+
+def desired_rung(params: dict, dt):
+    """The smallest r >= 0 whose step dt0 2^-r fits under the particle's limit
+    dt (min(dt_a, dt_CFL) >= 2^-r dt0); rung_max when none does."""
+    R = int(params.get("rung_max", 8))
+    dt0 = float(params.get("dt_max", 1.0))
+    dt = np.asarray(dt, dtype=np.float64)
+    out = np.full(dt.shape, R, dtype=np.int64)
+    for k in range(R, -1, -1):
+        out = np.where(dt >= math.ldexp(dt0, -k), k, out)
+    return out
+
+
+def neighbour_max_rung(params: dict, x, y, z, H, rung, rows):
+    """max_{j in F_i} r_j for the listed particles (-1 for an empty set)."""
+    off, idx = neighbors(params, x, y, z, H, mode=1)
+    out = np.full(len(rows), -1, dtype=np.int64)
+    for k, i in enumerate(rows):
+        nb = idx[off[i]:off[i + 1]]
+        if nb.size:
+            out[k] = int(np.max(rung[nb]))
+    return out
+
+
+def limit_rungs(r_des, nb_max):
+    """Saitoh-Makino: a particle's step is at most four times that of any
+    particle it interacts with, r_i >= r_j - 2."""
+    return np.maximum(r_des, nb_max - 2)
+
+
+def align_down(params: dict, r_old, r_new, T):
+    """A particle moves to a longer step only at a boundary of that step: the
+    lowest rung in [r_new, r_old] whose step divides T (moving up is free)."""
+    out = np.array(r_new, dtype=np.int64, copy=True)
+    for k in range(out.size):
+        if out[k] < r_old[k]:
+            r = int(out[k])
+            while int(T) % int(step_units(params, r)) != 0:
+                r += 1
+            out[k] = r
+    return out
+
+
+def predict_coeff(T, L, delta):
+    """Predictor weight at time T of a particle whose current step of L units
+    ends at or after T: (T - T_mid) delta, T_mid the middle of the step (at a
+    step end this is half the step, the predictor of the global scheme)."""
+    Tb = np.where(T % L == 0, T - L, T - T % L)
+    return ((T - Tb).astype(np.float64) - 0.5 * L.astype(np.float64)) * delta
+
+
+def _assign_rungs(params: dict, s: dict, rows, old):
+    R = int(params.get("rung_max", 8))
+    rd = desired_rung(params, s["dt"][rows])
+    nb = neighbour_max_rung(params, s["x"], s["y"], s["z"], s["H"], old, rows)
+    return np.minimum(limit_rungs(rd, nb), R)
+
+
+def rung_init(params: dict, state: dict) -> dict:
+    """init at T = 0, then every particle's rung: its desired rung, raised by
+    the limiter against the desired rungs of its force set (the same single
+    pass a rung update takes in a substep, where the neighbours' rungs are
+    those before the update)."""
+    s = init(params, state)
+    n = len(s["x"])
+    s["T"] = 0
+    rows = np.arange(n)
+    s["rung"] = _assign_rungs(params, s, rows, desired_rung(params, s["dt"]))
+    return s
+
+
+def substep(params: dict, s: dict) -> dict:
+    """One substep in place (Sec. 2.3.6): opening kick of the particles at a
+    step boundary, drift of all particles to the next boundary T', density of
+    all particles, prediction of v and u at T', EOS, forces of the particles
+    whose step ends at T' (the active ones), their closing kick and new rung.
+    Returns the report (dt = the substep's length, the active count)."""
+    R = int(params.get("rung_max", 8))
+    dt0 = float(params.get("dt_max", 1.0))
+    delta = math.ldexp(dt0, -R)
+    T = int(s["T"])
+    L = step_units(params, s["rung"])
+    at_boundary = (T % L) == 0
+    h = 0.5 * L.astype(np.float64) * delta
+    for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az"), ("u", "dudt")):
+        s[v] = np.where(at_boundary, s[v] + h * s[a], s[v])
+    Tn = int(np.min(T - T % L + L))
+    dT = Tn - T
+    for k, ax in (("x", 0), ("y", 1), ("z", 2)):
+        s[k] = _wrap(params, s[k] + (dT * delta) * s["v" + k], ax)
+    d = solve_h(params, s["x"], s["y"], s["z"], s["m"], s["H"])
+    s["H"], s["rho"], s["omega"] = d["H"], d["rho"], d["omega"]
+    cf = predict_coeff(np.int64(Tn), L, delta)
+    vxp = s["vx"] + cf * s["ax"]
+    vyp = s["vy"] + cf * s["ay"]
+    vzp = s["vz"] + cf * s["az"]
+    up = s["u"] + cf * s["dudt"]
+    s["P"], s["c"] = eos(params, s["rho"], up)
+    active = (Tn % L) == 0
+    rows = np.nonzero(active)[0]
+    f = forces(params, s["x"], s["y"], s["z"], vxp, vyp, vzp, s["m"], s["H"],
+               s["rho"], s["omega"], s["P"], s["c"], rows=rows)
+    for k in ("ax", "ay", "az", "dudt", "dt"):
+        s[k][rows] = f[k]
+    ha = h[rows]
+    for v, a in (("vx", "ax"), ("vy", "ay"), ("vz", "az"), ("u", "dudt")):
+        s[v][rows] = s[v][rows] + ha * s[a][rows]
+    old = s["rung"].copy()
+    rn = _assign_rungs(params, s, rows, old)
+    s["rung"][rows] = align_down(params, old[rows], rn, Tn)
+    s["T"] = Tn
+    s["n_d"] = int(d["count"].sum())
+    s["n_f"] = int(f["count"].sum())
+    return {"dt": dT * delta, "n_active": int(rows.size), "T": Tn}
