@@ -140,13 +140,39 @@ typedef struct {
                             the group's interaction-list length (candidate particles per
                             neighbour pair): long lists halve the buckets, short ones
                             double them.  The level is carried by the particles from step
-                            to step.  Results do not depend on it, only the cost. */
+                            to step.  Results do not depend on it, only the cost.
+                          SPH_FLAG_RUNGS: individual time steps (Sec. 2.3.6): particle i
+                            steps with dt_max 2^-r_i, its rung r_i in 0..rung_max the
+                            smallest with min(dt_a, dt_CFL) >= dt_max 2^-r_i, raised so
+                            that r_i >= r_j - 2 for every j of F_i (Saitoh-Makino; the
+                            neighbours' rungs before the update), moved to a longer step
+                            only at a boundary of that step.  sph_init assigns the rungs
+                            (the limiter against the neighbours' desired rungs); each
+                            sph_step is then one substep: opening kick of the particles
+                            at a step boundary, drift of all to the next boundary of any
+                            particle, density, prediction of v and u at that time
+                            (v_half + (t - t_mid) a for a step whose middle is t_mid),
+                            EOS, forces of the particles whose step ends there (the
+                            active ones), their closing kick and new rung.  With fastgas
+                            > 0 and fewer than fastgas n active particles, the density
+                            pass runs only for the particles on the interaction lists of
+                            the active ones (FastGas, Sec. 2.3.6, last paragraph: lists
+                            taken with the sinks' H widened by oversel).  Single-set
+                            contexts only; not combined with the other flags. */
     double ic_alpha;   /* normalisation alpha of the kernel imbalance (the paper gives no
                           value).  Default 10 (I near 1.5 at the free surface of a
                           uniform body). */
+    int32_t rung_max;  /* SPH_FLAG_RUNGS: finest rung, 0..20 (time is counted in units of
+                          dt_max 2^-rung_max).  Default 8. */
+    int32_t reserved2_;
+    double fastgas;    /* SPH_FLAG_RUNGS: active fraction below which the density pass is
+                          restricted (0 = never).  Default 0. */
 } sph_params;
 
-enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4, SPH_FLAG_DYNAMIC = 8 };
+enum {
+    SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4, SPH_FLAG_DYNAMIC = 8,
+    SPH_FLAG_RUNGS = 16
+};
 
 /* Caller-owned device arrays, n doubles each, caller particle order.
  * State: x y z (positions inside the periodic box), vx vy vz, m, u, H (and
@@ -156,12 +182,18 @@ enum { SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4, SPH_F
  * (continuity rate; only with SPH_FLAG_EVOLVED, may be NULL otherwise).
  * Interface correction (SPH_FLAG_INTERFACE): mat holds each particle's
  * material id (integer values; NULL = one material); imb and rhoc receive the
- * kernel imbalance and the corrected density (each may be NULL). */
+ * kernel imbalance and the corrected density (each may be NULL).
+ * Individual time steps (SPH_FLAG_RUNGS): rung holds each particle's rung
+ * (integer values, written by sph_init and the steps).  Between substeps a
+ * particle at a step boundary holds v and u at the current time, the others
+ * their half-step values; ax, ay, az, dudt and dt are those of each
+ * particle's last force pass. */
 typedef struct {
     double *x, *y, *z, *vx, *vy, *vz, *m, *u, *H;
     double *rho, *omega, *P, *c, *ax, *ay, *az, *dudt, *dt;
     double *drhodt;
     double *mat, *imb, *rhoc;
+    double *rung;
 } sph_particles;
 
 /* Counters of the most recent call, read with sph_get_stats. */
@@ -198,6 +230,13 @@ typedef struct {
     int64_t slots_force;          /* (before the per-particle filter), per pass */
     int64_t groups_by_level[4];   /* force-pass sink groups with buckets of 8, 16, 32, 64
                                      (SPH_FLAG_DYNAMIC; else all in the tree's size) */
+    int64_t t_units;              /* SPH_FLAG_RUNGS: time after the last call, in units of
+                                     dt_max 2^-rung_max (dt_used is the substep's length) */
+    int64_t n_active;             /* particles whose force was computed by the last call */
+    int64_t n_dens;               /* particles whose density was computed by the last call */
+    int64_t n_fastgas_miss;       /* force-set neighbours of active particles that FastGas
+                                     left out of the density pass (their density is that
+                                     of an earlier substep) */
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */

@@ -45,15 +45,16 @@ class Params(ctypes.Structure):
         ("h_max", c_double), ("oversel", c_double), ("nr_tol", c_double),
         ("nr_maxit", c_int32), ("bucket", c_int32), ("stack_limit", c_int32),
         ("flags", c_int32), ("ic_alpha", c_double),
+        ("rung_max", c_int32), ("reserved2_", c_int32), ("fastgas", c_double),
     ]
 
 
-FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE, FLAG_DYNAMIC = 1, 2, 4, 8
+FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE, FLAG_DYNAMIC, FLAG_RUNGS = 1, 2, 4, 8, 16
 
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H",
           "rho", "omega", "P", "c", "ax", "ay", "az", "dudt", "dt", "drhodt", "mat", "imb",
-          "rhoc")
+          "rhoc", "rung")
 
 
 class Particles(ctypes.Structure):
@@ -72,6 +73,8 @@ class Stats(ctypes.Structure):
         ("t_total_ms", c_double), ("n_iter_limit", c_int64), ("n_nonfinite", c_int64),
         ("n_retest", c_int64), ("status", c_int32), ("reserved_", c_int32),
         ("slots_density", c_int64), ("slots_force", c_int64), ("groups_by_level", c_int64 * 4),
+        ("t_units", c_int64), ("n_active", c_int64), ("n_dens", c_int64),
+        ("n_fastgas_miss", c_int64),
     ]
 
 
@@ -141,15 +144,16 @@ def make_params(p: dict) -> Params:
         q.box_lo[a] = float(lo[a])
         q.box_hi[a] = float(hi[a])
     for name in ("gamma", "P0", "alpha", "beta", "eps_av", "eta_c", "eta_a", "dt_max", "h_max",
-                 "oversel", "nr_tol", "ic_alpha"):
+                 "oversel", "nr_tol", "ic_alpha", "fastgas"):
         if name in p:
             setattr(q, name, float(p[name]))
-    for name in ("nr_maxit", "bucket", "stack_limit"):
+    for name in ("nr_maxit", "bucket", "stack_limit", "rung_max"):
         if name in p:
             setattr(q, name, int(p[name]))
     q.flags = ((FLAG_ENTROPY if p.get("entropy") else 0) | (FLAG_EVOLVED if p.get("evolved") else 0)
                | (FLAG_INTERFACE if p.get("interface") else 0)
-               | (FLAG_DYNAMIC if p.get("dynamic") else 0))
+               | (FLAG_DYNAMIC if p.get("dynamic") else 0)
+               | (FLAG_RUNGS if p.get("rungs") else 0))
     return q
 
 
@@ -161,7 +165,7 @@ def _stream_ptr(stream):
 
 
 class ParticleArrays:
-    """The 18 caller-owned FP64 device columns of include/sph.h (torch tensors)."""
+    """The caller-owned FP64 device columns of include/sph.h (torch tensors)."""
 
     def __init__(self, tensors: dict):
         self.t = tensors

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstddef>
+#include <climits>
 #include <new>
 
 using namespace sphmi;
@@ -61,6 +63,8 @@ void free_all(Ctx &c) {
     c.rho_old = c.rho_pred = c.rho_sum = c.drs = nullptr;
     c.mats = c.imbs = c.tbar = c.pbar = nullptr;
     c.levc = c.levs = c.d_levref = nullptr;
+    c.d_rung = nullptr; c.rungs = c.nbmax = c.nbmax_c = nullptr; c.rpack = nullptr;
+    c.rflags = nullptr; c.sinks = c.dsinks = c.mark = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
     if (c.h_rep) { (void)hipHostFree(c.h_rep); c.h_rep = nullptr; }
     if (c.h_flags) { (void)hipHostFree(c.h_flags); c.h_flags = nullptr; }
@@ -93,7 +97,8 @@ bool valid_params(const sph_params *p, std::string &why) {
     if (p->stack_limit != 0 && (p->stack_limit < 2 || p->stack_limit > kStackCap)) {
         why = "stack_limit must be 0 or 2..768"; return false;
     }
-    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED | SPH_FLAG_INTERFACE | SPH_FLAG_DYNAMIC)) {
+    if (p->flags & ~(SPH_FLAG_ENTROPY | SPH_FLAG_EVOLVED | SPH_FLAG_INTERFACE | SPH_FLAG_DYNAMIC |
+                     SPH_FLAG_RUNGS)) {
         why = "unknown flags"; return false;
     }
     if ((p->flags & SPH_FLAG_INTERFACE) && (p->flags & SPH_FLAG_EVOLVED)) {
@@ -106,6 +111,16 @@ bool valid_params(const sph_params *p, std::string &why) {
     if ((p->flags & SPH_FLAG_ENTROPY) && (p->flags & SPH_FLAG_EVOLVED)) {
         why = "the entropy-conserving update needs the summed density (not SPH_FLAG_EVOLVED)";
         return false;
+    }
+    if (p->flags & SPH_FLAG_RUNGS) {
+        if (p->flags != SPH_FLAG_RUNGS) {
+            why = "SPH_FLAG_RUNGS is not combined with the other flags"; return false;
+        }
+        if (p->rung_max < 0 || p->rung_max > 20) { why = "rung_max must be 0..20"; return false; }
+        if (!(p->dt_max > 0.0)) { why = "dt_max must be positive"; return false; }
+        if (!(p->fastgas >= 0.0 && p->fastgas <= 1.0)) {
+            why = "fastgas must be in [0, 1]"; return false;
+        }
     }
     return true;
 }
@@ -269,6 +284,11 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
     if (c.prm.flags & SPH_FLAG_EVOLVED) { A(c.rho_pred, n); A(c.rho_sum, n); A(c.drs, n); }
     if (c.prm.flags & SPH_FLAG_INTERFACE) { A(c.mats, n); A(c.imbs, n); A(c.tbar, n); A(c.pbar, n); }
     if (c.dyn) { A(c.levc, n); A(c.levs, n); A(c.d_levref, 1); }
+    if (c.rungs_on) {
+        A(c.d_rung, 1); A(c.rungs, n); A(c.nbmax, n); A(c.nbmax_c, n); A(c.rpack, n);
+        A(c.rflags, n + 1); A(c.sinks, n); A(c.dsinks, n);
+        if (c.prm.fastgas > 0.0) A(c.mark, n + 2);
+    }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, kCntShards * kCntStride);
@@ -317,6 +337,8 @@ sph_status check_particles(sph_ctx *x, const sph_particles *p, bool outputs, int
         return fail(x, SPH_ERR_INVALID, "an output array is NULL");
     if (outputs && x && (x->c.prm.flags & SPH_FLAG_EVOLVED) && !p->drhodt)
         return fail(x, SPH_ERR_INVALID, "drhodt is NULL (evolved density)");
+    if (x && (x->c.prm.flags & SPH_FLAG_RUNGS) && !p->rung)
+        return fail(x, SPH_ERR_INVALID, "rung is NULL (individual time steps)");
     return SPH_OK;
 }
 
@@ -380,6 +402,11 @@ sph_status do_density(sph_ctx *x, sph_particles *p, hipStream_t s, bool in_step 
     Cols g = cols0();
     g.src[0] = p->H; g.dst[0] = c.Hs; g.n = 1;
     if (c.dyn) { g.src[1] = c.levc; g.dst[1] = c.levs; g.n = 2; }
+    if (c.rungs_on && in_step) {
+        // (with FastGas the particles outside the density pass keep theirs)
+        g.src[g.n] = p->rho; g.dst[g.n] = c.rhos; ++g.n;
+        g.src[g.n] = p->omega; g.dst[g.n] = c.oms; ++g.n;
+    }
     HIPCHK(x, launch_gather(&c, g, s), "gather H");
     HIPCHK(x, launch_density(&c, s), "density");
     const bool keep_rho = in_step && (c.prm.flags & SPH_FLAG_EVOLVED);
@@ -437,7 +464,18 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
         HIPCHK(x, launch_interface_sums(&c, 1, s), "interface averages");
         HIPCHK(x, launch_ic_correct(&c, p->P, p->c, p->imb, p->rhoc, s), "interface correction");
     }
-    HIPCHK(x, launch_forces(&c, s), "forces");
+    const bool sub = c.rungs_on && in_step;   // a substep: the active sinks only
+    if (sub) {
+        c.sweep_sinks = c.sinks;
+        c.sweep_nsinks = reinterpret_cast<const long long *>(
+            reinterpret_cast<const char *>(c.d_rung) + offsetof(RungState, nact));
+    }
+    c.sweep_rpack = c.rungs_on && (in_step || c.rpack_ready);
+    const hipError_t fe = launch_forces(&c, s);
+    c.sweep_sinks = nullptr;
+    c.sweep_nsinks = nullptr;
+    c.sweep_rpack = false;
+    HIPCHK(x, fe, "forces");
     Cols o = cols0();
     o.src[0] = c.axs; o.dst[0] = p->ax;
     o.src[1] = c.ays; o.dst[1] = p->ay;
@@ -445,6 +483,14 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
     o.src[3] = c.dus; o.dst[3] = p->dudt;
     o.src[4] = c.dts; o.dst[4] = p->dt;
     o.n = 5;
+    if (c.rungs_on && (in_step || c.rpack_ready)) {
+        o.src[o.n] = c.nbmax; o.dst[o.n] = c.nbmax_c;
+        o.n += 1;
+    }
+    if (sub) {
+        HIPCHK(x, launch_scatter_sinks(&c, o, s), "scatter forces");
+        return SPH_OK;
+    }
     if (evolved) {
         o.src[o.n] = c.drs; o.dst[o.n] = p->drhodt;
         o.n += 1;
@@ -454,6 +500,81 @@ sph_status do_forces(sph_ctx *x, sph_particles *p, const double *vx, const doubl
         o.n += 1;
     }
     HIPCHK(x, launch_scatter(&c, o, s), "scatter forces");
+    return SPH_OK;
+}
+
+// Individual time steps: the device length of a sink list inside RungState.
+const long long *rung_count(const Ctx &c, size_t off) {
+    return reinterpret_cast<const long long *>(reinterpret_cast<const char *>(c.d_rung) + off);
+}
+
+hipError_t reset_rung_state(Ctx &c, hipStream_t s) {
+    unsigned long long *w = reinterpret_cast<unsigned long long *>(c.d_rung);
+    hipError_t e = launch_fill_u64(w, 4, 0ull, s);
+    if (e == hipSuccess) e = launch_fill_u64(w + 1, 1, (unsigned long long)LLONG_MAX, s);
+    if (e == hipSuccess) e = launch_fill_u64(w + 2, 2, (unsigned long long)c.n, s);
+    return e;
+}
+
+// Rungs at T = 0 (after the initial force pass): desired rungs from dt, then
+// a second force pass over them for the largest neighbour rung, then the
+// limiter (the forces of the second pass equal the first's).
+sph_status init_rungs(sph_ctx *x, sph_particles *p, hipStream_t s) {
+    Ctx &c = x->c;
+    HIPCHK(x, reset_rung_state(c, s), "rung state");
+    HIPCHK(x, launch_rung_desired(&c, p, s), "desired rungs");
+    Cols g = cols0();
+    g.src[0] = p->rung; g.dst[0] = c.rungs; g.n = 1;
+    HIPCHK(x, launch_gather(&c, g, s), "gather rungs");
+    HIPCHK(x, launch_rung_pack_init(&c, s), "pack rungs");
+    c.rpack_ready = true;
+    sph_status st = do_forces(x, p, p->vx, p->vy, p->vz, p->u, false, s);
+    c.rpack_ready = false;
+    if (st != SPH_OK) return st;
+    HIPCHK(x, launch_rung_limit_init(&c, p, s), "limiter");
+    return SPH_OK;
+}
+
+// One substep (Sec. 2.3.6): opening kick of the particles at a step
+// boundary, drift of all to the next boundary T', tree, density (all
+// particles, or with FastGas those on the active particles' lists), EOS and
+// forces of the active particles with v and u predicted at T', their closing
+// kick and new rung.
+sph_status do_substep(sph_ctx *x, sph_particles *p, hipStream_t s) {
+    Ctx &c = x->c;
+    HIPCHK(x, reset_counters(c, s), "counters");
+    HIPCHK(x, launch_rung_open(&c, p, s), "opening kick");
+    HIPCHK(x, launch_rung_drift(&c, p, s), "drift");
+    HIPCHK(x, launch_tree_build(&c, p, s), "tree");
+    Cols g = cols0();
+    g.src[0] = p->rung; g.dst[0] = c.rungs; g.n = 1;
+    HIPCHK(x, launch_gather(&c, g, s), "gather rungs");
+    HIPCHK(x, launch_rung_lists(&c, false, s), "active sinks");
+    const bool fg = c.prm.fastgas > 0.0;
+    if (fg) {
+        HIPCHK(x, launch_fill_u64(reinterpret_cast<unsigned long long *>(c.mark), (c.n + 2) / 2, 0ull,
+                                  s), "marks");
+        c.sweep_sinks = c.sinks;
+        c.sweep_nsinks = rung_count(c, offsetof(RungState, nact));
+        const hipError_t e = launch_mark(&c, s);
+        c.sweep_sinks = nullptr;
+        c.sweep_nsinks = nullptr;
+        HIPCHK(x, e, "FastGas marks");
+        HIPCHK(x, launch_rung_dens_list(&c, s), "density sinks");
+        c.sweep_sinks = c.dsinks;
+        c.sweep_nsinks = rung_count(c, offsetof(RungState, ndens));
+    }
+    sph_status st = do_density(x, p, s, true);
+    c.sweep_sinks = nullptr;
+    c.sweep_nsinks = nullptr;
+    if (st != SPH_OK) return st;
+    HIPCHK(x, launch_rung_pack(&c, s), "pack rungs");
+    st = do_forces(x, p, c.vpx, c.vpy, c.vpz, c.upred, false, s, true);
+    if (st != SPH_OK) return st;
+    HIPCHK(x, launch_rung_close(&c, p, s), "closing kick");
+    HIPCHK(x, launch_rung_finish(&c, s), "substep end");
+    HIPCHK(x, launch_reduce(&c, p, s), "reduce");
+    mark(&c, E_END, s);
     return SPH_OK;
 }
 
@@ -553,6 +674,8 @@ void sph_default_params(sph_params *p) {
     p->nr_maxit = 64;
     p->bucket = 32;
     p->ic_alpha = 10.0;
+    p->rung_max = 8;
+    p->fastgas = 0.0;
 }
 
 const char *sph_version(void) { return kVersion; }
@@ -567,6 +690,7 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
     if (!valid_params(params, why)) return SPH_ERR_INVALID;
     if (nsets < 1 || nsets > 4096) return SPH_ERR_INVALID;
     if (nsets > 1 && !set_offsets) return SPH_ERR_INVALID;
+    if (nsets > 1 && (params->flags & SPH_FLAG_RUNGS)) return SPH_ERR_INVALID;
     if (set_offsets) {
         if (set_offsets[0] != 0) return SPH_ERR_INVALID;
         for (int q = 0; q < nsets; ++q)
@@ -586,6 +710,7 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
     if (!(c.prm.nr_tol > 0))
         c.prm.nr_tol = c.prm.precision == SPH_PREC_MIXED ? 1e-5 : 1e-14;
     c.dyn = (c.prm.flags & SPH_FLAG_DYNAMIC) != 0;
+    c.rungs_on = (c.prm.flags & SPH_FLAG_RUNGS) != 0;
     c.base_bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
     c.bucket = c.dyn ? 8 : c.base_bucket;   // (dynamic sizing: the tree's buckets are the finest)
     if (c.prm.stack_limit == 0) c.prm.stack_limit = kStackCap;
@@ -730,6 +855,10 @@ sph_status sph_init(sph_ctx *ctx, sph_particles *p, int64_t n, void *stream) {
         HIPCHK(ctx, launch_copy(c.rho_old, p->rho, c.n, s), "rho_old");
     st = do_forces(ctx, p, p->vx, p->vy, p->vz, p->u, false, s);
     if (st != SPH_OK) return st;
+    if (c.rungs_on) {
+        st = init_rungs(ctx, p, s);
+        if (st != SPH_OK) return st;
+    }
     HIPCHK(ctx, launch_reduce(&c, p, s), "reduce");
     HIPCHK(ctx, launch_set_dtnext(&c, p, s), "set dt");
     mark(&c, E_END, s);
@@ -749,7 +878,9 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream) {
     st = take_status(ctx);
     if (st != SPH_OK) return st;
     c.last_stream = s;
-    st = do_step(ctx, p, dt, s);
+    if (c.rungs_on && dt > 0.0)
+        return fail(ctx, SPH_ERR_INVALID, "with individual time steps dt must be <= 0");
+    st = c.rungs_on ? do_substep(ctx, p, s) : do_step(ctx, p, dt, s);
     if (st == SPH_OK) HIPCHK(ctx, post_status(c, s), "status");
     return st;
 }
@@ -759,6 +890,8 @@ sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, voi
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Ctx &c = ctx->c;
     if (!c.have_forces) return fail(ctx, SPH_ERR_STATE, "call sph_init before capturing a step");
+    if (c.rungs_on)
+        return fail(ctx, SPH_ERR_INVALID, "individual time steps are not captured as a graph");
     sph_status st = check_particles(ctx, p, true, c.n);
     if (st != SPH_OK) return st;
     if (!s) return fail(ctx, SPH_ERR_INVALID, "graph capture needs a non-null stream");
@@ -825,6 +958,16 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->slots_density = (int64_t)c.h_cnt[C_SLOTS_D];
     out->slots_force = (int64_t)c.h_cnt[C_SLOTS_F];
     for (int q = 0; q < 4; ++q) out->groups_by_level[q] = (int64_t)c.h_cnt[C_LEV0 + q];
+    out->n_active = c.n;
+    out->n_dens = c.n;
+    if (c.rungs_on && c.d_rung) {
+        RungState rs;
+        HIPCHK(ctx, hipMemcpy(&rs, c.d_rung, sizeof(rs), hipMemcpyDeviceToHost), "rung state");
+        out->t_units = rs.T;
+        out->n_active = rs.nact;
+        out->n_dens = c.prm.fastgas > 0.0 ? rs.ndens : c.n;
+        out->n_fastgas_miss = (int64_t)c.h_cnt[C_FGMISS];
+    }
     c.status_pending = false;   // reported here, not again by the next call
     auto span = [&](int a, int b) -> double {
         if (!((c.ev_mask >> a) & 1u) || !((c.ev_mask >> b) & 1u)) return -1.0;
@@ -908,6 +1051,7 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
 sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t n, void *stream) {
     std::string why;
     if (!valid_params(params, why)) return SPH_ERR_INVALID;
+    if (params->flags & SPH_FLAG_RUNGS) return SPH_ERR_INVALID;   // (a global step only)
     if (n < 0) return SPH_ERR_INVALID;
     if (n > kNoAllocMaxN) return SPH_ERR_CAPACITY;   // beyond the static work space
     if (check_particles(nullptr, p, true, n) != SPH_OK) return SPH_ERR_INVALID;

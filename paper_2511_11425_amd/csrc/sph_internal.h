@@ -28,6 +28,7 @@ enum Counter {
     C_RETEST,                             // mixed pairs re-tested in FP64 (exact membership)
     C_SLOTS_D, C_SLOTS_F,                 // candidate slots loaded (interaction-list lengths)
     C_LEV0, C_LEV1, C_LEV2, C_LEV3,       // force-pass sink groups per bucket level
+    C_FGMISS,                             // FastGas: force pairs with a stale neighbour density
     C_NTRANSIENT,                         // counters above are cleared by every call
     C_PAIRS_D_TOT = C_NTRANSIENT,         // running totals since the context was made
     C_PAIRS_F_TOT,
@@ -62,6 +63,12 @@ struct StepReport {
     double dt_next;   // min_i dt_i of the last force pass, capped by dt_max
     double dt_used;   // dt of the last step
     double pad;
+};
+
+// Individual time steps: the time T and the next step boundary in units of
+// dt_max 2^-rung_max, the active and density-pass particle counts.
+struct RungState {
+    long long T, Tnext, nact, ndens;
 };
 
 // Per-set geometry shared by all kernels (device array, one entry per set).
@@ -151,6 +158,23 @@ struct Ctx {
     double *d_levref = nullptr;// mean list length per pair of the last force pass (one value;
                                // kept off the counters' cache line, which the sweeps' atomics
                                // keep busy)
+    // individual time steps (device): time, next boundary, active and
+    // density counts; sorted rungs, packed rungs, sink lists and marks
+    RungState *d_rung = nullptr;
+    double *rungs = nullptr;   // sorted: rung
+    double *nbmax = nullptr;   // sorted: largest rung over F_i (force pass)
+    int32_t *rpack = nullptr;  // sorted: rung | 256 when the density is not of this substep
+    int64_t *rflags = nullptr; // n + 1: compaction flags, then their exclusive scan
+    uint32_t *sinks = nullptr, *dsinks = nullptr;   // active sinks, density sinks (sorted)
+    uint32_t *mark = nullptr;  // sorted: FastGas marks
+    double *nbmax_c = nullptr; // caller order: nbmax of the active particles
+    bool rungs_on = false;
+    // what the next sweep launches take: a sink list and its device length
+    // (null: all particles), the packed rungs (null: no rung maximum)
+    const uint32_t *sweep_sinks = nullptr;
+    const long long *sweep_nsinks = nullptr;
+    bool sweep_rpack = false;
+    bool rpack_ready = false;   // sph_init: the desired rungs are packed (limiter pass)
     bool mats_has = false;     // the caller gave material ids
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 
@@ -215,6 +239,19 @@ struct Cols {
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 // zero counters [0, last) of every copy; fold the copies into d_csum
 hipError_t launch_reset_counters(Ctx *c, int last, hipStream_t s);
+// individual time steps (Sec. 2.3.6)
+hipError_t launch_rung_open(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_rung_drift(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_rung_lists(Ctx *c, bool fastgas, hipStream_t s);
+hipError_t launch_rung_dens_list(Ctx *c, hipStream_t s);
+hipError_t launch_rung_close(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_rung_finish(Ctx *c, hipStream_t s);
+hipError_t launch_rung_desired(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_rung_limit_init(Ctx *c, sph_particles *p, hipStream_t s);
+hipError_t launch_rung_pack(Ctx *c, hipStream_t s);
+hipError_t launch_scatter_sinks(Ctx *c, const Cols &cols, hipStream_t s);   // active sinks only
+hipError_t launch_mark(Ctx *c, hipStream_t s);
+hipError_t launch_rung_pack_init(Ctx *c, hipStream_t s);   // no FastGas flags
 hipError_t launch_fold_counters(Ctx *c, hipStream_t s);
 hipError_t launch_gather(Ctx *c, const Cols &cols, hipStream_t s);   // dst[k] = src[perm[k]]
 hipError_t launch_scatter(Ctx *c, const Cols &cols, hipStream_t s);  // dst[perm[k]] = src[k]

@@ -7,6 +7,8 @@
 #include "sph_internal.h"
 
 #include <cfloat>
+#include <climits>
+#include <cstddef>
 
 namespace sphmi {
 
@@ -386,6 +388,198 @@ __global__ __launch_bounds__(kRedBlocks) void k_reduce_final(const double *__res
     }
 }
 
+
+// ---- individual time steps (Sec. 2.3.6) ---------------------------------------
+// Time is counted in units of delta = dt_max 2^-R (R = rung_max); a particle
+// on rung r steps L = 2^(R-r) units and its steps start at multiples of L.
+// Caller order unless noted; the arithmetic follows the oracle's order.
+
+__device__ __forceinline__ long long rung_step(double r, int R) {
+    int k = (int)r;
+    k = k < 0 ? 0 : (k > R ? R : k);
+    return 1ll << (R - k);
+}
+
+// The smallest rung whose step dt_max 2^-r fits under dt; R when none does
+// (NaN included).
+__device__ __forceinline__ int desired_rung(double dt, double dt0, int R) {
+    for (int k = 0; k <= R; ++k)
+        if (dt >= ldexp(dt0, -k)) return k;
+    return R;
+}
+
+// Opening kick of the particles at a step boundary, v_half = v + (L/2) delta a
+// (u likewise), and the next step boundary of any particle (one atomic
+// minimum per wave).
+__global__ void k_rung_open(int64_t n, int R, double delta, RungState *rs,
+                            const double *__restrict__ rung, double *vx, double *vy, double *vz,
+                            double *u, const double *__restrict__ ax, const double *__restrict__ ay,
+                            const double *__restrict__ az, const double *__restrict__ du) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long nxt = LLONG_MAX;
+    if (i < n) {
+        const long long T = rs->T;
+        const long long L = rung_step(rung[i], R);
+        if (T % L == 0) {
+            const double h = 0.5 * (double)L * delta;
+            vx[i] = vx[i] + h * ax[i];
+            vy[i] = vy[i] + h * ay[i];
+            vz[i] = vz[i] + h * az[i];
+            u[i] = u[i] + h * du[i];
+        }
+        nxt = T - T % L + L;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long w = __shfl_xor(nxt, o);
+        nxt = w < nxt ? w : nxt;
+    }
+    if ((threadIdx.x & 63) == 0 && nxt != LLONG_MAX)
+        atomicMin(reinterpret_cast<unsigned long long *>(&rs->Tnext), (unsigned long long)nxt);
+}
+
+// Drift of every particle to the next boundary T', x += (T' - T) delta v
+// (wrapped), and the prediction at T': v_pred = v + ((T' - Tb) - L/2) delta a
+// with Tb the start of the particle's current step (u likewise).
+__global__ void k_rung_drift(int64_t n, int R, double delta, const RungState *rs,
+                             const double *__restrict__ rung, double *x, double *y, double *z,
+                             const double *__restrict__ vx, const double *__restrict__ vy,
+                             const double *__restrict__ vz, const double *__restrict__ u,
+                             const double *__restrict__ ax, const double *__restrict__ ay,
+                             const double *__restrict__ az, const double *__restrict__ du,
+                             double *vpx, double *vpy, double *vpz, double *up, int periodic,
+                             const SetGeom *sets) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long T = rs->T, Tn = rs->Tnext;
+    const double dx = (double)(Tn - T) * delta;
+    double nx = x[i] + dx * vx[i];
+    double ny = y[i] + dx * vy[i];
+    double nz = z[i] + dx * vz[i];
+    if (periodic) {
+        const SetGeom &g = sets[0];
+        nx = wrap_box(nx, g.lo[0], g.L[0]);
+        ny = wrap_box(ny, g.lo[1], g.L[1]);
+        nz = wrap_box(nz, g.lo[2], g.L[2]);
+    }
+    x[i] = nx; y[i] = ny; z[i] = nz;
+    const long long L = rung_step(rung[i], R);
+    const long long Tb = (Tn % L == 0) ? Tn - L : Tn - Tn % L;
+    const double cf = ((double)(Tn - Tb) - 0.5 * (double)L) * delta;
+    vpx[i] = vx[i] + cf * ax[i];
+    vpy[i] = vy[i] + cf * ay[i];
+    vpz[i] = vz[i] + cf * az[i];
+    up[i] = u[i] + cf * du[i];
+}
+
+// Sorted order: the active sinks (whose step ends at T') in ascending order.
+__global__ void k_rung_flags(int64_t n, int R, const RungState *rs, const double *__restrict__ rungs,
+                             int64_t *flags) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) flags[k] = (rs->Tnext % rung_step(rungs[k], R) == 0) ? 1 : 0;
+    else if (k == n) flags[k] = 0;
+}
+__global__ void k_rung_compact(int64_t n, int R, RungState *rs, const double *__restrict__ rungs,
+                               const int64_t *__restrict__ offs, uint32_t *sinks) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && rs->Tnext % rung_step(rungs[k], R) == 0) sinks[offs[k]] = (uint32_t)k;
+    if (k == n) rs->nact = offs[n];
+}
+
+// FastGas: below fastgas n active particles the density sinks are the marked
+// particles, else all of them.
+__global__ void k_dens_flags(int64_t n, double thr, const RungState *rs,
+                             const uint32_t *__restrict__ mark, int64_t *flags) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool fg = (double)rs->nact < thr * (double)n;
+    if (k < n) flags[k] = (!fg || mark[k]) ? 1 : 0;
+    else if (k == n) flags[k] = 0;
+}
+__global__ void k_dens_compact(int64_t n, double thr, RungState *rs,
+                               const uint32_t *__restrict__ mark, const int64_t *__restrict__ offs,
+                               uint32_t *sinks) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool fg = (double)rs->nact < thr * (double)n;
+    if (k < n && (!fg || mark[k])) sinks[offs[k]] = (uint32_t)k;
+    if (k == n) rs->ndens = offs[n];
+}
+
+// Sorted order: rung | 256 for particles whose density is not of this substep.
+__global__ void k_rung_pack(int64_t n, const double *__restrict__ rungs,
+                            const uint32_t *__restrict__ mark, double thr, const RungState *rs,
+                            int32_t *rpack) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    bool fresh = true;
+    if (mark) fresh = !((double)rs->nact < thr * (double)n) || mark[k] != 0;
+    rpack[k] = (int32_t)rungs[k] | (fresh ? 0 : 256);
+}
+
+// Closing kick of the active particles, v = v_half + (L/2) delta a_new (u
+// likewise), then the new rung: desired, raised to max_{F_i} r_j - 2, capped at
+// R, and when longer than the old step, the lowest rung whose step divides T'.
+__global__ void k_rung_close(int64_t n, int R, double dt0, double delta, const RungState *rs,
+                             double *rung, double *vx, double *vy, double *vz, double *u,
+                             const double *__restrict__ ax, const double *__restrict__ ay,
+                             const double *__restrict__ az, const double *__restrict__ du,
+                             const double *__restrict__ dt, const double *__restrict__ nbmax) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long Tn = rs->Tnext;
+    const long long L = rung_step(rung[i], R);
+    if (Tn % L != 0) return;
+    const double h = 0.5 * (double)L * delta;
+    vx[i] = vx[i] + h * ax[i];
+    vy[i] = vy[i] + h * ay[i];
+    vz[i] = vz[i] + h * az[i];
+    u[i] = u[i] + h * du[i];
+    const int r_old = (int)rung[i];
+    int r = desired_rung(dt[i], dt0, R);
+    const int lim = (int)nbmax[i] - 2;
+    r = r > lim ? r : lim;
+    r = r < R ? r : R;
+    if (r < r_old)
+        while (Tn % rung_step((double)r, R) != 0) ++r;
+    rung[i] = (double)r;
+}
+
+// End of a substep: its length into the report, T = T', next boundary unset.
+__global__ void k_rung_finish(RungState *rs, double delta, StepReport *rep) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    rep->dt_used = (double)(rs->Tnext - rs->T) * delta;
+    rs->T = rs->Tnext;
+    rs->Tnext = LLONG_MAX;
+}
+
+// Initial rungs: desired ones, then the limiter against the neighbours'
+// desired rungs (nbmax from a force pass over the desired rungs).
+__global__ void k_rung_desired(int64_t n, int R, double dt0, const double *__restrict__ dt,
+                               double *rung) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rung[i] = (double)desired_rung(dt[i], dt0, R);
+}
+__global__ void k_rung_limit_init(int64_t n, int R, double dt0, const double *__restrict__ dt,
+                                  const double *__restrict__ nbmax, double *rung) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int r = desired_rung(dt[i], dt0, R);
+    const int lim = (int)nbmax[i] - 2;
+    r = r > lim ? r : lim;
+    rung[i] = (double)(r < R ? r : R);
+}
+
+// Sorted-order columns of the listed sinks into caller order.
+__global__ void k_scatter_sinks(const uint32_t *__restrict__ perm, const uint32_t *__restrict__ sinks,
+                                const long long *__restrict__ nsinks, Cols c) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *nsinks) return;
+    const uint32_t i = sinks[k];
+    const uint32_t o = perm[i];
+    for (int q = 0; q < kMaxCols; ++q)
+        if (q < c.n) c.dst[q][o] = c.src[q][i];
+}
 }  // namespace
 
 int reduce_partials() { return kRedBlocks; }
@@ -498,6 +692,103 @@ hipError_t launch_reduce(Ctx *c, const sph_particles *p, hipStream_t s) {
     k_reduce_part<<<kRedBlocks, kThreads, 0, s>>>(c->n, p->m, p->vx, p->vy, p->vz, p->u, p->dt,
                                                    c->d_part);
     k_reduce_final<<<1, kRedBlocks, 0, s>>>(c->d_part, c->prm.dt_max, c->d_rep);
+    return hipGetLastError();
+}
+
+
+// ---- individual time steps: launchers ------------------------------------------
+
+namespace {
+inline double rung_delta(const Ctx *c) { return ldexp(c->prm.dt_max, -c->prm.rung_max); }
+}  // namespace
+
+hipError_t launch_rung_open(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_rung_open<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->n, c->prm.rung_max, rung_delta(c), c->d_rung, p->rung, p->vx, p->vy, p->vz, p->u,
+        p->ax, p->ay, p->az, p->dudt);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_drift(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_rung_drift<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->n, c->prm.rung_max, rung_delta(c), c->d_rung, p->rung, p->x, p->y, p->z, p->vx, p->vy,
+        p->vz, p->u, p->ax, p->ay, p->az, p->dudt, c->vpx, c->vpy, c->vpz, c->upred,
+        c->prm.periodic, c->d_sets);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_lists(Ctx *c, bool fastgas, hipStream_t s) {
+    (void)fastgas;
+    const int64_t n = c->n;
+    k_rung_flags<<<nblk(n + 1, kThreads), kThreads, 0, s>>>(n, c->prm.rung_max, c->d_rung,
+                                                           c->rungs, c->rflags);
+    hipError_t e = launch_scan_i64(c, c->rflags, c->rflags, n + 1, s);
+    if (e != hipSuccess) return e;
+    k_rung_compact<<<nblk(n + 1, kThreads), kThreads, 0, s>>>(n, c->prm.rung_max, c->d_rung,
+                                                             c->rungs, c->rflags, c->sinks);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_dens_list(Ctx *c, hipStream_t s) {
+    const int64_t n = c->n;
+    k_dens_flags<<<nblk(n + 1, kThreads), kThreads, 0, s>>>(n, c->prm.fastgas, c->d_rung, c->mark,
+                                                           c->rflags);
+    hipError_t e = launch_scan_i64(c, c->rflags, c->rflags, n + 1, s);
+    if (e != hipSuccess) return e;
+    k_dens_compact<<<nblk(n + 1, kThreads), kThreads, 0, s>>>(n, c->prm.fastgas, c->d_rung,
+                                                             c->mark, c->rflags, c->dsinks);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_pack(Ctx *c, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    const bool fg = c->prm.fastgas > 0.0 && c->mark;
+    k_rung_pack<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->rungs, fg ? c->mark : nullptr,
+                                                         c->prm.fastgas, c->d_rung, c->rpack);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_close(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_rung_close<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->n, c->prm.rung_max, c->prm.dt_max, rung_delta(c), c->d_rung, p->rung, p->vx, p->vy,
+        p->vz, p->u, p->ax, p->ay, p->az, p->dudt, p->dt, c->nbmax_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_finish(Ctx *c, hipStream_t s) {
+    k_rung_finish<<<1, 64, 0, s>>>(c->d_rung, rung_delta(c), c->d_rep);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_desired(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_rung_desired<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->prm.rung_max,
+                                                            c->prm.dt_max, p->dt, p->rung);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_limit_init(Ctx *c, sph_particles *p, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_rung_limit_init<<<nblk(c->n, kThreads), kThreads, 0, s>>>(
+        c->n, c->prm.rung_max, c->prm.dt_max, p->dt, c->nbmax_c, p->rung);
+    return hipGetLastError();
+}
+
+hipError_t launch_rung_pack_init(Ctx *c, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    k_rung_pack<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->n, c->rungs, nullptr, 0.0, c->d_rung,
+                                                         c->rpack);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_sinks(Ctx *c, const Cols &cols, hipStream_t s) {
+    if (c->n == 0) return hipSuccess;
+    const long long *nact = reinterpret_cast<const long long *>(
+        reinterpret_cast<const char *>(c->d_rung) + offsetof(RungState, nact));
+    k_scatter_sinks<<<nblk(c->n, kThreads), kThreads, 0, s>>>(c->d_perm[0], c->sinks, nact, cols);
     return hipGetLastError();
 }
 

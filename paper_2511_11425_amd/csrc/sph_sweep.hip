@@ -539,7 +539,43 @@ struct SweepArgs {
     const int64_t *offsets; // caller order (fill pass)
     int32_t *idx;
     uint32_t *wstack;       // walk stacks of the sweeps (kStackCap per sink group)
+    // individual time steps: sink lists (sorted indices of the sinks; null: a
+    // group is a run of 64 consecutive particles) and their lengths (device),
+    // each particle's rung packed with a FastGas flag (rung | 256 when its
+    // density is not of this substep), the largest rung over F_i (out), marks
+    const uint32_t *sinks;
+    const long long *nsinks;
+    const int32_t *rpack;
+    double *nbmax;
+    uint32_t *mark;
+    double fastgas;         // active fraction below which FastGas marks
 };
+
+// The sinks of group grp: sorted indices i (one per lane) and whether the
+// lane holds one.  With a sink list the groups are its runs of 64 entries;
+// groups past its end have no sinks (the caller returns before any barrier).
+__device__ __forceinline__ bool group_sinks(const SweepArgs &a, const SetGeom &g, int64_t grp,
+                                            int64_t &i, bool &act) {
+    const int lane = threadIdx.x;
+    if (a.sinks) {
+        const int64_t kb = grp * kGroup;
+        const int64_t ns = *a.nsinks;
+        if (kb >= ns) return false;
+        act = kb + lane < ns;
+        i = (int64_t)a.sinks[act ? kb + lane : kb];
+        return true;
+    }
+    i = g.p0 + (grp - g.g0) * kGroup + lane;
+    act = i < g.p1;
+    return true;
+}
+
+// Sorted index of the sink of lane s of group grp (band re-tests).
+__device__ __forceinline__ int64_t sink_index(const SweepArgs &a, const SetGeom &g, int64_t grp,
+                                              int s) {
+    if (a.sinks) return (int64_t)a.sinks[grp * kGroup + s];
+    return g.p0 + (grp - g.g0) * kGroup + s;
+}
 
 __device__ __forceinline__ double set_slop(const SetGeom &g) {
     return 1e-9 * (g.L[0] + g.L[1] + g.L[2]);
@@ -559,13 +595,12 @@ __device__ __forceinline__ double set_hcap(const SetGeom &g, bool per, double h_
 // any of its particles carries from the previous step (the most refined
 // wins), so a region whose lists blew up keeps small buckets after the
 // particles are re-sorted.
-__device__ __forceinline__ int group_bucket(const SweepArgs &a, SetGeom &g, int64_t i0, bool act,
+__device__ __forceinline__ int group_bucket(const SweepArgs &a, SetGeom &g, int64_t i, bool act,
                                             int &level) {
     int B = a.B;
     level = 0;
     if (!a.levs) return B;
-    const int lane = threadIdx.x;
-    int h = (int)wave_min(act ? a.levs[i0 + lane] : 1e30);
+    int h = (int)wave_min(act ? a.levs[i] : 1e30);
     h = h < 0 ? 0 : h;
     h = h > a.lev_max ? a.lev_max : h;
     h = h > g.depth ? g.depth : h;
@@ -948,11 +983,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     const bool per = a.periodic != 0;
     const double slop = set_slop(g);
     const double cap = set_hcap(g, per, a.h_max);
-    const int64_t i0 = g.p0 + (grp - g.g0) * kGroup;   // the group's first sink
-    const int64_t i = i0 + lane;
-    const bool act = i < g.p1;
+    int64_t i;
+    bool act;
+    if (!group_sinks(a, g, grp, i, act)) return;
     int level;
-    const int Bg = group_bucket(a, g, i0, act, level);   // this group's bucket size
+    const int Bg = group_bucket(a, g, i, act, level);   // this group's bucket size
     const int lb = 31 - __builtin_clz((unsigned)Bg);     // Bg = 2^lb
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double mi = act ? a.ms[i] : 0.0;
@@ -1122,8 +1157,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
                         bool in = false;
                         if (act_) {
                             const double Hs = sH[s_];
-                            in = exact_inside(a.xs, a.ys, a.zs, i0 + s_, (int64_t)tj[k_], Hs * Hs,
-                                              per, g);
+                            in = exact_inside(a.xs, a.ys, a.zs, sink_index(a, g, grp, s_),
+                                              (int64_t)tj[k_], Hs * Hs, per, g);
                             if (!in) atomicAdd(&srej[s_], 1);
                         }
                         retests += __popcll(__ballot(act_));
@@ -1301,7 +1336,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // distance tests, the fourth wave of the mixed kernel (128 VGPRs, 52 of its
 // values spilled to scratch) cost more than it hid (2M mixed forces 3.81 ms
 // at four waves, 3.24 at three).
-template <int K, bool MIXED>
+template <int K, bool MIXED, bool RUNGS>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_forces(SweepArgs a) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
@@ -1334,6 +1369,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
     __shared__ double acc[5][kWave];   // a_x a_y a_z du/dt, sum m (v_ij . x_ij) G_i
     __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
+    // individual time steps: largest rung over F_i, sorted index of each sink,
+    // pairs whose neighbour's density is not of this substep (FastGas)
+    __shared__ int armax[RUNGS ? kWave : 1], asidx[RUNGS ? kWave : 1], amiss[1];
 
     const int lane = threadIdx.x;
     const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
@@ -1343,11 +1381,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     SetGeom g = a.sets[sid];
     const bool per = a.periodic != 0;
     const double slop = set_slop(g);
-    const int64_t i0 = g.p0 + (grp - g.g0) * kGroup;   // the group's first sink
-    const int64_t i = i0 + lane;
-    const bool act = i < g.p1;
+    int64_t i;
+    bool act;
+    if (!group_sinks(a, g, grp, i, act)) return;
     int level;
-    const int Bg = group_bucket(a, g, i0, act, level);   // this group's bucket size
+    const int Bg = group_bucket(a, g, i, act, level);   // this group's bucket size
     const int lb = 31 - __builtin_clz((unsigned)Bg);     // Bg = 2^lb
     const double lref = a.levs_out ? *a.lev_ref : 0.0;    // (for the level rule at the end)
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
@@ -1401,6 +1439,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), (R)(sigma_of<K>() * h2_i * h2_i * hinv_i)};
     for (int q = 0; q < 5; ++q) acc[q][lane] = 0;
     amu[lane] = 0;
+    if constexpr (RUNGS) {
+        armax[lane] = -1;
+        asidx[lane] = act ? (int)i : -1;
+        if (lane == 0) amiss[0] = 0;
+    }
     const R alpha = (R)a.alpha, beta = (R)a.beta, eps = (R)a.eps;
     const R pdv = a.entropy ? R(0) : R(1);   // PdV part of du/dt (off: entropy-conserving)
     const bool evolved = a.drho != nullptr;
@@ -1479,7 +1522,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                     if (MIXED && WRAP) h2 *= wfac;
                     return push_hit(b, r2, hi2 > h2 ? hi2 : h2);
                 };
-                struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; };
+                struct PF { int s; R x, y, z, m; V4<R> cv, cq, ip, iv, iq; int j, rp; };
                 tile_pairs<1>(ring, [&](int k0, uint32_t b) {
 #pragma unroll
                     for (int h = 0; h < 8; h += 4) {
@@ -1492,12 +1535,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                     }
                     return b;
                 }, [&](int s, int k) {
+                    int jr = 0, rp = 0;
+                    if constexpr (RUNGS) { jr = tj[k]; rp = a.rpack[jr]; }
                     if constexpr (MIXED)
                         return PF{s, tx[k], ty[k], tz[k], trm[k], trec1[k], trec2[k], sp[s], sv[s],
-                                  sq[s]};
+                                  sq[s], jr, rp};
                     const int32_t j = tj[k];
                     return PF{s, tx[k], ty[k], tz[k], (R)a.ms[j], rec1[j], rec2[j], sp[s], sv[s],
-                              sq[s]};
+                              sq[s], jr, rp};
                 }, [&](const PF &d, bool valid, bool decided) -> bool {
                     const int s = d.s;
                     const V4<R> &cv = d.cv, &cq = d.cq, &ip = d.ip, &iv = d.iv, &iq = d.iq;
@@ -1553,13 +1598,21 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
                         if (evolved) atomicAdd(&acc[4][s], (double)(mj * vdotx * Gi));
                         if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
+                    if constexpr (RUNGS) {
+                        // F_i without i itself (a coincident j counts)
+                        if (valid && d.j != asidx[s]) {
+                            atomicMax(&armax[s], d.rp & 255);
+                            if (d.rp >> 8) atomicAdd(&amiss[0], 1);
+                        }
+                    }
                     return false;
                 }, [&](int s_, int k_, bool act_) -> bool {
                     bool in = false;
                     if (act_) {
                         const int64_t jj = (int64_t)tj[k_];
-                        const double hi_ = a.Hs[i0 + s_], hj_ = a.Hs[jj];
-                        in = exact_inside(a.xs, a.ys, a.zs, i0 + s_, jj,
+                        const int64_t si_ = sink_index(a, g, grp, s_);
+                        const double hi_ = a.Hs[si_], hj_ = a.Hs[jj];
+                        in = exact_inside(a.xs, a.ys, a.zs, si_, jj,
                                           fmax(hi_ * hi_, hj_ * hj_), per, g);
                     }
                     retests += __popcll(__ballot(act_));
@@ -1657,6 +1710,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         a.dt[i] = dtv;
         nonfinite = !isfinite(dtv) || !isfinite(acc_d[3]);
         if (evolved) a.drho[i] = acc_d[4] / a.oms[i];
+        if constexpr (RUNGS) a.nbmax[i] = (double)armax[lane];
     }
     // the particle itself passed the distance test once (r = 0)
     int pairs_n = wave_sum_i(act ? cnt - 1 : 0) - rej;
@@ -1678,6 +1732,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         if (act) a.levs_out[i] = (double)hn;
     }
     if (lane == 0) {
+        if (RUNGS && amiss[0]) atomicAdd(&ctr[C_FGMISS], (unsigned long long)amiss[0]);
         atomicAdd(&ctr[C_SLOTS_F], slots);
         atomicAdd(&ctr[C_LEV0 + level], 1ull);
         if (nnan) atomicAdd(&ctr[C_NONFINITE], (unsigned long long)nnan);
@@ -1732,7 +1787,7 @@ __global__ __launch_bounds__(kWave) void k_gather_sums(SweepArgs a) {
     const int64_t i = g.p0 + (grp - g.g0) * kGroup + lane;
     const bool act = i < g.p1;
     int level;
-    const int Bg = group_bucket(a, g, g.p0 + (grp - g.g0) * kGroup, act, level);
+    const int Bg = group_bucket(a, g, i, act, level);
     const int lb = 31 - __builtin_clz((unsigned)Bg);
     const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
     const double H = act ? a.Hs[i] : 0.0;
@@ -2016,6 +2071,52 @@ __global__ __launch_bounds__(256) void k_sort_rows(const int64_t *__restrict__ o
     for (int t = threadIdx.x; t < len; t += blockDim.x) idx[b + t] = v[t];
 }
 
+
+// FastGas marking (Sec. 2.3.6, last paragraph), below fastgas n active
+// particles: every particle of a bucket on the interaction list of an active
+// sink group is marked, and so are the sinks; the density pass then runs for
+// the marked particles only.  The lists are taken with the sinks' balls
+// widened to oversel H and their cell bound by (oversel - 1) times their
+// largest H, so that the smoothing lengths of this substep's density pass,
+// which move little over a substep, keep the force sets of the active
+// particles inside them (the force pass counts any neighbour left out).
+__global__ __launch_bounds__(kWave) void k_mark(SweepArgs a) {
+    __shared__ uint32_t cand[kCandCap];
+    const int lane = threadIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    if (!((double)*a.nsinks < a.fastgas * (double)(a.sets[0].p1 - a.sets[0].p0))) return;
+    uint32_t *const stack = a.wstack + grp * kStackCap;
+    const SetGeom g = a.sets[0];
+    const bool per = a.periodic != 0;
+    const double slop = set_slop(g);
+    int64_t i;
+    bool act;
+    if (!group_sinks(a, g, grp, i, act)) return;
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    const double Hd = act ? a.Hs[i] : 0.0;
+    if (act) a.mark[i] = 1u;
+    Sink sk;
+    sink_bounds(act, xi, a.oversel * Hd, sk);
+    const double grow = (a.oversel - 1.0) * wave_max(act ? Hd : 0.0);
+    for (int q = 0; q < 3; ++q) { sk.clo[q] -= grow; sk.chi[q] += grow; }
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
+    walk_reset(stack, ws, false, g);
+    while (true) {
+        walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        if (ws.overflow) {
+            walk_reset(stack, ws, true, g);
+            continue;
+        }
+        for (int t0 = 0; t0 < ws.ncand; t0 += kWave / a.B) {
+            const int64_t j = slot_index(g, cand, ws.ncand, t0, a.B);
+            if (j >= 0) a.mark[j] = 1u;
+        }
+        __syncthreads();   // (the next walk step rewrites cand)
+        if (ws.nstack == 0) break;
+        ws.ncand = 0;
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 inline SweepArgs base_args(Ctx *c) {
@@ -2045,6 +2146,12 @@ inline SweepArgs base_args(Ctx *c) {
     a.stack_limit = c->prm.stack_limit;
     a.alpha = c->prm.alpha; a.beta = c->prm.beta; a.eps = c->prm.eps_av;
     a.eta_a = c->prm.eta_a; a.eta_c = c->prm.eta_c; a.dt_max = c->prm.dt_max;
+    a.sinks = c->sweep_sinks;
+    a.nsinks = c->sweep_nsinks;
+    a.rpack = c->sweep_rpack ? c->rpack : nullptr;
+    a.nbmax = c->nbmax;
+    a.mark = c->mark;
+    a.fastgas = c->prm.fastgas;
     return a;
 }
 
@@ -2063,11 +2170,20 @@ hipError_t density_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
 template <bool MIXED>
 hipError_t forces_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
     dim3 grid((unsigned)c->ngroups), block(kWave);
+    if (a.rpack) {
+        switch (c->prm.kernel) {
+        case 0: k_forces<0, MIXED, true><<<grid, block, 0, s>>>(a); break;
+        case 1: k_forces<1, MIXED, true><<<grid, block, 0, s>>>(a); break;
+        case 2: k_forces<2, MIXED, true><<<grid, block, 0, s>>>(a); break;
+        default: k_forces<3, MIXED, true><<<grid, block, 0, s>>>(a); break;
+        }
+        return hipGetLastError();
+    }
     switch (c->prm.kernel) {
-    case 0: k_forces<0, MIXED><<<grid, block, 0, s>>>(a); break;
-    case 1: k_forces<1, MIXED><<<grid, block, 0, s>>>(a); break;
-    case 2: k_forces<2, MIXED><<<grid, block, 0, s>>>(a); break;
-    default: k_forces<3, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 0: k_forces<0, MIXED, false><<<grid, block, 0, s>>>(a); break;
+    case 1: k_forces<1, MIXED, false><<<grid, block, 0, s>>>(a); break;
+    case 2: k_forces<2, MIXED, false><<<grid, block, 0, s>>>(a); break;
+    default: k_forces<3, MIXED, false><<<grid, block, 0, s>>>(a); break;
     }
     return hipGetLastError();
 }
@@ -2113,6 +2229,13 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
         e = hipGetLastError();
     }
     return e;
+}
+
+hipError_t launch_mark(Ctx *c, hipStream_t s) {
+    if (c->ngroups == 0) return hipSuccess;
+    SweepArgs a = base_args(c);
+    k_mark<<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_interface_sums(Ctx *c, int mode, hipStream_t s) {

@@ -1,0 +1,172 @@
+"""Individual time steps (Sec. 2.3.6) on the GPU against the oracle, through
+the C interface: rungs at initialisation, then substeps over a whole base
+step (opening kick of the particles at a step boundary, drift to the next
+boundary, density, prediction, forces of the active particles, closing kick
+and new rung with the Saitoh-Makino limiter), with and without FastGas.
+
+Bars: rungs and active counts exact (integers); the substep lengths exact;
+FP64 positions 1e-12 absolute, v, u, rho, H 1e-11 relative after the base
+step (the bars of the global-step trajectories).  FastGas: the same bars
+against the oracle, whose density pass covers every particle, and no force
+pair may meet a density of an earlier substep.  Mixed: the rungs of at least
+99 % of the particles equal the oracle's after the base step (a limit within
+FP32 rounding of a step boundary may pick the other rung).
+"""
+import copy
+
+import numpy as np
+import pytest
+
+import sph_inputs as si
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sph():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_11425_amd as m
+    return m
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300))
+
+
+def hot_lattice(n_side=12, seed=7, hot=30.0, vsig=0.05):
+    """Jittered periodic lattice with a hot sphere (u 30x) in the middle."""
+    rng = np.random.default_rng(seed)
+    x, y, z, a = si.jittered_lattice(rng, n_side)
+    n = x.size
+    r2 = (x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2
+    u = np.where(r2 < 0.15 ** 2, hot, 1.0)
+    st = dict(x=x, y=y, z=z, vx=rng.normal(0, vsig, n), vy=rng.normal(0, vsig, n),
+              vz=rng.normal(0, vsig, n), m=np.full(n, 1.0 / n), u=u,
+              H=np.full(n, si._h_guess(a, 60)))
+    return st, si.params(kernel="wc2", n_ngb=60.0)
+
+
+@pytest.fixture(scope="module")
+def hot(orc):
+    """u 300x in the hot sphere: five populated rungs, and the limiter changes
+    rung updates inside the base step."""
+    st, p = hot_lattice(hot=300.0)
+    s0 = orc.init(p, st)
+    p = dict(p, dt_max=float(1.5 * s0["dt"].max()), rung_max=7, rungs=True)
+    return st, p
+
+
+def test_initial_rungs(sph, orc, hot):
+    st, p = hot
+    ref = orc.rung_init(p, st)
+    P = sph.ParticleArrays.from_state(st)
+    ctx = sph.Context(p)
+    print("rung init", flush=True)
+    ctx.init(P)
+    got = P.numpy()
+    assert np.array_equal(got["rung"], ref["rung"].astype(np.float64))
+    assert len(np.unique(ref["rung"])) >= 3
+    assert rel(got["dt"], ref["dt"]) < 1e-12
+    st_ = ctx.stats()
+    assert st_["t_units"] == 0 and st_["n_active"] == len(st["x"])
+
+
+@pytest.fixture(scope="module")
+def hot_wide(orc):
+    """The hot sphere in a box of 20^3 particles: the interaction lists of the
+    hot particles cover a fraction of the box (FastGas restricts the density
+    pass)."""
+    st, p = hot_lattice(n_side=20, hot=300.0)
+    s0 = orc.init(p, st)
+    p = dict(p, dt_max=float(1.5 * s0["dt"].max()), rung_max=7, rungs=True)
+    return st, p
+
+
+@pytest.mark.parametrize("fastgas", [0.0, 1.0], ids=["all-density", "fastgas"])
+def test_base_step_of_substeps_fp64(sph, orc, hot, hot_wide, fastgas):
+    st, p = hot_wide if fastgas > 0 else hot
+    p = dict(p, fastgas=fastgas)
+    ref = orc.rung_init(p, st)
+    P = sph.ParticleArrays.from_state(st)
+    ctx = sph.Context(p)
+    print(f"substeps fp64 fastgas={fastgas}", flush=True)
+    ctx.init(P)
+    n = len(st["x"])
+    k = 0
+    restricted = 0
+    limited = 0
+    while ref["T"] < (1 << p["rung_max"]):
+        old = ref["rung"].copy()
+        rep = orc.substep(p, ref)
+        # updates whose result the limiter changed (the check is not vacuous)
+        rows = np.nonzero(rep["T"] % orc.step_units(p, old) == 0)[0]
+        rd = orc.desired_rung(p, ref["dt"][rows])
+        free = orc.align_down(p, old[rows], np.minimum(rd, p["rung_max"]), rep["T"])
+        limited += int(np.sum(ref["rung"][rows] != free))
+        ctx.step(P)
+        s_ = ctx.stats()
+        k += 1
+        assert s_["t_units"] == rep["T"], k
+        assert s_["n_active"] == rep["n_active"], k
+        assert s_["dt_used"] == rep["dt"], k
+        assert s_["n_fastgas_miss"] == 0, k
+        if s_["n_dens"] < n:
+            restricted += 1
+        got = P.numpy()
+        bad = np.nonzero(got["rung"] != ref["rung"])[0]
+        for i in bad[:5]:
+            print(f"  substep {k} particle {i}: rung {got['rung'][i]} oracle {ref['rung'][i]}"
+                  f" dt {got['dt'][i]!r} oracle {ref['dt'][i]!r}", flush=True)
+        assert bad.size == 0, k
+    print(f"  {k} substeps, {restricted} with a restricted density pass, {limited} updates "
+          f"set by the limiter", flush=True)
+    assert limited > (10 if fastgas == 0 else 0)
+    if fastgas > 0:
+        assert restricted > 0
+    got = P.numpy()
+    for key in ("x", "y", "z"):
+        assert np.max(np.abs(got[key] - ref[key])) < 1e-12, key
+    for key in ("vx", "vy", "vz"):
+        assert np.max(np.abs(got[key] - ref[key])) < 1e-11 * np.max(np.abs(ref[key])), key
+    assert rel(got["u"], ref["u"]) < 1e-11
+    # the density of the last substep: with FastGas only where it was computed
+    if fastgas == 0:
+        assert rel(got["rho"], ref["rho"]) < 1e-11
+        assert rel(got["H"], ref["H"]) < 1e-11
+
+
+def test_base_step_of_substeps_mixed(sph, orc, hot):
+    st, p = hot
+    ref = orc.rung_init(p, st)
+    P = sph.ParticleArrays.from_state(st)
+    ctx = sph.Context(dict(p, precision="mixed"))
+    print("substeps mixed", flush=True)
+    ctx.init(P)
+    assert np.mean(P.numpy()["rung"] == ref["rung"]) > 0.99
+    while ref["T"] < (1 << p["rung_max"]):
+        orc.substep(p, ref)
+    k = 0
+    while ctx.stats()["t_units"] < (1 << p["rung_max"]) and k < 200:
+        ctx.step(P)
+        k += 1
+    got = P.numpy()
+    agree = np.mean(got["rung"] == ref["rung"])
+    e = np.max(np.abs(got["x"] - ref["x"]))
+    print(f"  {k} substeps, rungs agree {agree:.4f}, x err {e:.2e}", flush=True)
+    assert agree > 0.99
+    assert ctx.stats()["t_units"] == 1 << p["rung_max"]
+
+
+def test_rung_combinations_rejected(sph, hot):
+    st, p = hot
+    for extra in ({"entropy": True}, {"interface": True}, {"dynamic": True},
+                  {"rung_max": 21}):
+        with pytest.raises(sph.SphError):
+            sph.Context(dict(p, **extra))
+    P = sph.ParticleArrays.from_state(st)
+    ctx = sph.Context(p)
+    ctx.init(P)
+    with pytest.raises(sph.SphError):
+        ctx.step(P, dt=1e-3)

@@ -54,6 +54,16 @@ def hot(orc):
     return st, p
 
 
+@pytest.fixture(scope="module")
+def hotter(orc):
+    """u 300x in the hot sphere: five populated rungs, and the limiter changes
+    rung updates inside the base step, not only at T = 0."""
+    st, p = hot_lattice(hot=300.0)
+    s0 = orc.init(p, st)
+    p = dict(p, dt_max=float(1.5 * s0["dt"].max()), rung_max=7)
+    return st, p
+
+
 def run_base_step(orc, p, s, check=None):
     s = copy.deepcopy(s)
     reps = []
@@ -123,19 +133,27 @@ def limiter_check(orc, hot):
     raised = int(np.sum(s["rung"] > rd))
     # at T = 0 the rungs the limiter looks at are the desired ones
     b0, _ = limiter_violations(orc, p, dict(s, rung=rd), s, {"T": 0})
-    tally = {"bad": b0, "updated": 0}
+    tally = {"bad": b0, "updated": 0, "changed": 0}
 
     def check(before, after, rep):
         b, n = limiter_violations(orc, p, before, after, rep)
         tally["bad"] += b
         tally["updated"] += n
+        # updates whose result the limiter changed (against the desired rung
+        # moved down as far as the update time allows)
+        old = before["rung"]
+        rows = np.nonzero(rep["T"] % orc.step_units(p, old) == 0)[0]
+        rd_ = orc.desired_rung(p, after["dt"][rows])
+        free = orc.align_down(p, old[rows], np.minimum(rd_, p["rung_max"]), rep["T"])
+        tally["changed"] += int(np.sum(after["rung"][rows] != free))
     run_base_step(orc, p, s, check)
     return raised, tally
 
 
-def test_limiter_holds_at_every_update(orc, hot):
-    raised, tally = limiter_check(orc, hot)
-    assert raised > 0             # the limiter acts on this input
+def test_limiter_holds_at_every_update(orc, hotter):
+    raised, tally = limiter_check(orc, hotter)
+    assert raised > 0             # the limiter acts at T = 0 ...
+    assert tally["changed"] > 10  # ... and in the substeps
     assert tally["updated"] > 1000
     assert tally["bad"] == 0
 
@@ -222,6 +240,8 @@ def test_second_order_against_finest_rung(orc, hot):
 MUTANTS = {
     "limiter_off": ("limit_rungs", lambda orc: (lambda r_des, nb: r_des),
                     lambda orc, hot: limiter_check(orc, hot)[1]["bad"] > 0),
+    "limiter_only_at_start": ("_assign_rungs", None,
+                              lambda orc, hot: limiter_check(orc, hot)[1]["bad"] > 0),
     "down_anytime": ("align_down", lambda orc: (lambda p, r_old, r_new, T: np.asarray(r_new)),
                      lambda orc, hot: alignment_check(orc, hot)["n"] > 0),
     "predict_to_step_end": ("predict_coeff",
@@ -230,12 +250,28 @@ MUTANTS = {
 }
 
 
+def _limiter_only_at_start(orc):
+    """Rung updates inside the base step skip the limiter (T = 0 keeps it)."""
+    keep = orc._assign_rungs
+
+    def assign(params, s, rows, old):
+        if len(rows) == len(s["x"]) and s["T"] == 0:
+            return keep(params, s, rows, old)
+        R = int(params.get("rung_max", 8))
+        return np.minimum(orc.desired_rung(params, s["dt"][rows]), R)
+    return assign
+
+
+MUTANTS["limiter_only_at_start"] = ("_assign_rungs", _limiter_only_at_start,
+                                    MUTANTS["limiter_only_at_start"][2])
+
+
 @pytest.mark.parametrize("name", sorted(MUTANTS))
-def test_rung_pins_reject_planted_mistakes(orc, hot, name):
+def test_rung_pins_reject_planted_mistakes(orc, hot, hotter, name):
     fn, make, caught = MUTANTS[name]
     keep = getattr(orc, fn)
     setattr(orc, fn, make(orc))
     try:
-        assert caught(orc, hot), name
+        assert caught(orc, hotter if name.startswith("limiter") else hot), name
     finally:
         setattr(orc, fn, keep)
