@@ -11,7 +11,10 @@ value  = pair interactions per second of the whole step for the mixed path:
          wall time of the timed steps (tree build and kick included).
 Also reported: the same for the FP64 path, the density+force-only rate of
 the metric's definition (kernel times from HIP events inside the library),
-the roofline of the dominant kernel and the FP64 CPU oracle on a sample.
+the roofline of the dominant kernel, the per-field errors of each precision
+against the stored FP64 oracle trajectory of the workload (a fresh run of
+init + its steps, sampled particles), and the FP64 CPU oracle on a sample
+(all threads and one thread).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--small]
 """
@@ -65,7 +68,6 @@ def make_workload(name, small=False):
         st = {k: np.concatenate([x[k] for x in b["sets"]]) for k in keys}
         offs = np.concatenate([[0], np.cumsum([len(x["x"]) for x in b["sets"]])]).tolist()
         c = {"state": st, "params": b["params"], "set_offsets": offs, "graph": True,
-             "autotune": True,
              "desc": f"{len(b['sets'])} independent periodic boxes of 4096-65536 particles, "
                      f"cubic spline, 64 neighbours"}
     elif name == "spheres":
@@ -78,6 +80,7 @@ def make_workload(name, small=False):
     else:
         raise ValueError(name)
     c["workload"] = name
+    c["autotune"] = True   # (the bucket size the library's autotuner picks)
     c["n"] = len(c["state"]["x"])
     offs = c.get("set_offsets") or [0, c["n"]]
     c["ngroups"] = _ngroups(np.diff(offs))
@@ -192,6 +195,56 @@ def run_gpu(case, precision, steps, warmup, graph=False):
     return res
 
 
+GOLDEN = {"large": ("large_fp64_10steps.json", 10), "spheres": ("spheres_1step.json", 1)}
+
+
+def errors_vs_oracle(case, precision, bucket):
+    """Per-field errors of a fresh run (init + the stored number of global
+    steps, this precision) against the FP64 oracle trajectory stored under
+    tests/golden for this workload, on its sampled particles: x absolute, v
+    relative to max |v|, u rho H relative, a relative to the rms of |a| over
+    all particles, du/dt relative to its rms, dt of the last step relative."""
+    import torch
+    import paper_2511_11425_amd as sph
+    if case["workload"] not in GOLDEN or case.get("schemes"):
+        return None
+    name, steps = GOLDEN[case["workload"]]
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    if g["n"] != case["n"]:
+        return None
+    rows = np.asarray(g["rows"])
+    P = sph.ParticleArrays.from_state(case["state"], device="cuda:0")
+    ctx = sph.Context(dict(case["params"], precision=precision, bucket=bucket))
+    ctx.init(P)
+    for _ in range(steps):
+        ctx.step(P)
+    st = ctx.stats()
+    got = P.numpy()
+    ctx.close()
+    del P
+    torch.cuda.empty_cache()
+    fin, rec = g["final"], g["records"][-1]
+    out = {"x": max(float(np.max(np.abs(got[k][rows] - np.asarray(fin[k])))) for k in "xyz")}
+    vmax = max(float(np.max(np.abs(fin[k]))) for k in ("vx", "vy", "vz"))
+    out["v"] = max(float(np.max(np.abs(got[k][rows] - np.asarray(fin[k])))) for k in
+                   ("vx", "vy", "vz")) / vmax
+    for k in ("u", "rho", "H"):
+        ref = np.asarray(fin[k])
+        out[k] = float(np.max(np.abs(got[k][rows] - ref) / np.abs(ref)))
+    out["a"] = max(float(np.max(np.abs(got[k][rows] - np.asarray(fin[k])))) for k in
+                   ("ax", "ay", "az")) / rec["rms_a"]
+    out["dudt"] = float(np.max(np.abs(got["dudt"][rows] - np.asarray(fin["dudt"])))) / \
+        rec["rms_dudt"]
+    out["dt"] = abs(st["dt_used"] - rec["dt"]) / rec["dt"]
+    out["reference"] = (f"FP64 oracle, {len(rows)} sampled particles after init and "
+                        f"{steps} global step(s) ({name})")
+    return out
+
+
 def traffic_of(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when that summary was taken on a different kernel source or workload."""
@@ -232,7 +285,19 @@ def cpu_baseline(case, seconds=15.0):
     fixed = max(p1["secs"] - per_row * r1, 0.0)
     rows = int(min(n, max(r1, (seconds / 3 - fixed) / per_row)))
     runs = [_oracle_sample(case, rows, final=True) for _ in range(3)]
-    return sorted(runs, key=lambda r: r["value"])[1]
+    out = sorted(runs, key=lambda r: r["value"])[1]
+    # one thread: the same per-row cost on fewer rows (median of 3)
+    import oracle
+    cores = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        rows1 = max(2000, rows // max(cores, 1))
+        one = sorted((_oracle_sample(case, rows1, final=True) for _ in range(3)),
+                     key=lambda r: r["value"])[1]
+    finally:
+        oracle.set_threads(cores)
+    out["single_thread"] = {"value": one["value"], "cores": 1, "sample": one["sample"]}
+    return out
 
 
 def _oracle_sample(case, nrows, final=False):
@@ -272,6 +337,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the per-field errors against the stored oracle trajectory")
     ap.add_argument("--small", action="store_true", help="64^3 instead of 128^3 (quick check)")
     ap.add_argument("--precisions", default="mixed,fp64")
     ap.add_argument("--workload", default="large", choices=list(WORKLOADS))
@@ -303,6 +370,7 @@ def main():
         if k not in SCHEMES:
             ap.error(f"unknown scheme {k}")
     case = with_scheme(make_workload(args.workload, args.small), schemes)
+    case["schemes"] = schemes
     if args.bucket:
         case = dict(case, params=dict(case["params"], bucket=args.bucket), autotune=False)
     graph = args.graph or case.get("graph", False)
@@ -335,6 +403,11 @@ def main():
         if mixed:
             roof["peak_unpacked"] = PEAK_F32_UNPACKED / 1e12
             roof["frac_unpacked"] = achieved / PEAK_F32_UNPACKED
+    errs = {}
+    if not args.no_verify:
+        for prec in results:
+            log(f"errors against the oracle, {prec}")
+            errs[prec] = errors_vs_oracle(case, prec, results[prec]["bucket"])
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
@@ -366,6 +439,7 @@ def main():
                                        "cand_force", "nr_scans_mean", "n_overflow",
                                        "slots_density", "slots_force", "groups_by_level")},
         "roofline": roof,
+        "errors_vs_oracle": errs or None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

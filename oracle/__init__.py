@@ -60,6 +60,7 @@ def configure(L):
     L.orc_sigma.restype = c_double
     L.orc_sigma.argtypes = [c_int]
     L.orc_num_threads.restype = c_int
+    L.orc_set_threads.argtypes = [c_int]
     L.orc_params_size.restype = c_int
     L.orc_kernel_shape.argtypes = [c_int, c_int64, dp, dp, dp]
     L.orc_kernel_w.argtypes = [c_int, c_int64, dp, dp, dp, dp, dp]
@@ -164,6 +165,11 @@ def _i(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's row loops (its results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 def sigma(kernel) -> float:

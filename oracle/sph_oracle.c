@@ -74,6 +74,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the row loops (timing only: rows are independent). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_params_size(void) { return (int)sizeof(orc_params); }
 
 /* ------------------------------------------------------------------------ */
