@@ -394,7 +394,8 @@ def main():
             flops = head["pairs_density"] * FLOP_DENSITY_PAIR * head["nr_scans_mean"]
             t = head["t_density_ms"] * 1e-3
         kidx = KERNEL_INDEX[case["params"].get("kernel", "m4")]
-        kname = f"k_{dom}<{kidx}, {'true' if mixed else 'false'}>"
+        kname = f"k_{dom}<{kidx}, {'true' if mixed else 'false'}" + \
+            (", false>" if dom == "forces" else ">")   # (forces: no rung maximum)
         achieved = flops / t
         roof = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                 "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],

@@ -199,7 +199,12 @@ typedef struct {
 /* Counters of the most recent call, read with sph_get_stats. */
 typedef struct {
     int64_t n;                    /* particles */
-    int64_t pairs_density;        /* sum_i |G_i| at the converged H */
+    int64_t pairs_density;        /* sum_i |G_i| at the H of the last scan of the candidates;
+                                     the iteration may then take a last step of at most
+                                     sqrt(nr_tol) H (FP64) or 2e-3 H (mixed) without another
+                                     scan, so a pair within that distance of the final support
+                                     may be counted on the other side (at 2M particles, FP64:
+                                     within 1e-7 of the oracle's count at its H) */
     int64_t pairs_force;          /* sum_i |F_i| */
     int64_t cand_density;         /* candidate particles tested, summed over sinks and scans */
     int64_t cand_force;           /* candidate particles tested in the force pass */
