@@ -195,7 +195,8 @@ def run_gpu(case, precision, steps, warmup, graph=False):
     return res
 
 
-GOLDEN = {"large": ("large_fp64_10steps.json", 10), "spheres": ("spheres_1step.json", 1)}
+GOLDEN = {"large": ("large_fp64_10steps.json", 10), "two_phase": ("two_phase_fp64_3steps.json", 3),
+          "spheres": ("spheres_1step.json", 1)}
 
 
 def errors_vs_oracle(case, precision, bucket):

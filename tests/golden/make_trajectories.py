@@ -6,13 +6,16 @@ with.  Calls only the oracle and the seeded input generators.
                            counts after init and after each of 10 global
                            steps, and the state of 400 sampled particles
                            after init and after the 10 steps.
+  two_phase_fp64_3steps.json  128^3 lattice with a slab of density 10 in
+                           density 1 (pressure equilibrium, shear flow): the
+                           same record after init and three steps.
   spheres_1step.json       two spheres in vacuum (12 000 000 + 4 800 000
                            particles, stiffened gas): reductions and pair
                            counts after init and one step, and the state of
                            400 sampled particles after init and after the
                            step.
 
-Usage: python tests/golden/make_trajectories.py [large|spheres]...
+Usage: python tests/golden/make_trajectories.py [large|two_phase|spheres]...
 (all-thread oracle; the large case takes minutes, the spheres tens of them)
 """
 import json
@@ -67,9 +70,11 @@ def trajectory(case, steps, nsample, seed, out):
 
 
 def main():
-    which = sys.argv[1:] or ["large", "spheres"]
+    which = sys.argv[1:] or ["large", "two_phase", "spheres"]
     if "large" in which:
         trajectory(si.config_large(), 10, 400, 2024, "large_fp64_10steps.json")
+    if "two_phase" in which:
+        trajectory(si.config_two_phase(), 3, 400, 2026, "two_phase_fp64_3steps.json")
     if "spheres" in which:
         trajectory(si.config_spheres(), 1, 400, 2025, "spheres_1step.json")
 

@@ -21,6 +21,9 @@ graph:
     smallest, the largest, one between) at the trajectory bars;
   * mixed: the same three sets after init against the oracle (rho 1e-5
     relative, a 1e-4 of the rms, du/dt 1e-3 of the rms).
+The 128^3 two-phase slab (density 10 in 1), three global steps against the
+stored oracle trajectory (tests/golden/two_phase_fp64_3steps.json), both
+precisions.
 Two spheres in vacuum, 16.8M particles (stiffened gas), one full step
 against the stored oracle step (tests/golden/spheres_1step.json): FP64 at
 the trajectory bars; mixed: rho and H 1e-5 relative, a 1e-4 of the rms of
@@ -155,6 +158,44 @@ def test_large_ten_fp64_steps_against_stored_oracle(sph, large):
     e1 = s["e_kin"] + s["e_int"]
     print(f"  energy drift over ten steps {abs(e1 - e0) / e0:.2e}", flush=True)
     assert abs(e1 - e0) <= 1e-4 * e0
+
+
+# ---- two-phase slab -------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_two_phase_three_steps_against_stored_oracle(sph, precision):
+    """128^3 slab of density 10 in density 1: three global steps against the
+    stored FP64 oracle trajectory (tests/golden/two_phase_fp64_3steps.json).
+    FP64: x 1e-11 absolute, v, u, rho, H 1e-11 relative, a and du/dt 1e-11 of
+    their rms; mixed: x 1e-7, rho and H 1e-5 relative, a 1e-4 and du/dt 1e-3
+    of the rms, dt 1e-5 relative."""
+    g = load("two_phase_fp64_3steps.json")
+    c = si.config_two_phase()
+    st, p = c["state"], c["params"]
+    assert g["n"] == len(st["x"])
+    rows = np.asarray(g["rows"])
+    P = sph.ParticleArrays.from_state(st)
+    ctx = sph.Context(dict(p, precision=precision))
+    print(f"2M two-phase slab, three steps, {precision}", flush=True)
+    ctx.init(P)
+    for _ in range(3):
+        ctx.step(P)
+    s = ctx.stats()
+    got = P.numpy()
+    f, rec = g["final"], g["records"][-1]
+    if precision == "fp64":
+        tx, tr, ta, td, tdt = 1e-11, 1e-11, 1e-11, 1e-11, 1e-12
+    else:
+        tx, tr, ta, td, tdt = 1e-7, 1e-5, 1e-4, 1e-3, 1e-5
+    assert abs(s["dt_used"] - rec["dt"]) <= tdt * rec["dt"]
+    for k in ("x", "y", "z"):
+        assert np.max(np.abs(got[k][rows] - f[k])) < tx, k
+    for k in ("rho", "H"):
+        assert rel(got[k][rows], f[k]) < tr, k
+    for k in ("ax", "ay", "az"):
+        assert np.max(np.abs(got[k][rows] - f[k])) < ta * rec["rms_a"], k
+    assert np.max(np.abs(got["dudt"][rows] - f["dudt"])) < td * rec["rms_dudt"]
+    print(f"  rho err {rel(got['rho'][rows], f['rho']):.2e}", flush=True)
 
 
 # ---- 256 boxes ----------------------------------------------------------------------
