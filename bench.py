@@ -183,6 +183,8 @@ def run_gpu(case, precision, steps, warmup, graph=False):
         "n_overflow": st["n_overflow"],
         "slots_density": st["slots_density"], "slots_force": st["slots_force"],
         "groups_by_level": list(st["groups_by_level"]),
+        "launch": "persistent" if st["launch"] == sph.LAUNCH_PERSISTENT else "groups",
+        "workgroups_force": st["workgroups_force"],
     }
     if tden:
         res.update({"t_density_ms": float(np.mean(tden)), "t_forces_ms": float(np.mean(tfor)),
@@ -199,7 +201,7 @@ GOLDEN = {"large": ("large_fp64_10steps.json", 10), "two_phase": ("two_phase_fp6
           "spheres": ("spheres_1step.json", 1)}
 
 
-def errors_vs_oracle(case, precision, bucket):
+def errors_vs_oracle(case, precision, bucket, launch):
     """Per-field errors of a fresh run (init + the stored number of global
     steps, this precision) against the FP64 oracle trajectory stored under
     tests/golden for this workload, on its sampled particles: x absolute, v
@@ -219,7 +221,7 @@ def errors_vs_oracle(case, precision, bucket):
         return None
     rows = np.asarray(g["rows"])
     P = sph.ParticleArrays.from_state(case["state"], device="cuda:0")
-    ctx = sph.Context(dict(case["params"], precision=precision, bucket=bucket))
+    ctx = sph.Context(dict(case["params"], precision=precision, bucket=bucket, launch=launch))
     ctx.init(P)
     for _ in range(steps):
         ctx.step(P)
@@ -346,6 +348,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay one captured step as a HIP graph")
     ap.add_argument("--bucket", type=int, default=0,
                     help="bucket size 8, 16, 32 or 64 (default: the workload's)")
+    ap.add_argument("--launch", default="", choices=["", "groups", "persistent"],
+                    help="sweep launch shape (default: the autotuner's choice)")
     ap.add_argument("--scheme", default="",
                     help="comma list of optional schemes: " + ",".join(SCHEMES))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -374,6 +378,8 @@ def main():
     case["schemes"] = schemes
     if args.bucket:
         case = dict(case, params=dict(case["params"], bucket=args.bucket), autotune=False)
+    if args.launch:
+        case = dict(case, params=dict(case["params"], launch=args.launch), autotune=False)
     graph = args.graph or case.get("graph", False)
     results = {}
     for prec in args.precisions.split(","):
@@ -395,8 +401,9 @@ def main():
             flops = head["pairs_density"] * FLOP_DENSITY_PAIR * head["nr_scans_mean"]
             t = head["t_density_ms"] * 1e-3
         kidx = KERNEL_INDEX[case["params"].get("kernel", "m4")]
+        persist = "true" if head["launch"] == "persistent" else "false"
         kname = f"k_{dom}<{kidx}, {'true' if mixed else 'false'}" + \
-            (", false>" if dom == "forces" else ">")   # (forces: no rung maximum)
+            (f", false, {persist}>" if dom == "forces" else f", {persist}>")   # (forces: no rung maximum)
         achieved = flops / t
         roof = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                 "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],
@@ -409,7 +416,8 @@ def main():
     if not args.no_verify:
         for prec in results:
             log(f"errors against the oracle, {prec}")
-            errs[prec] = errors_vs_oracle(case, prec, results[prec]["bucket"])
+            errs[prec] = errors_vs_oracle(case, prec, results[prec]["bucket"],
+                                          results[prec]["launch"])
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
@@ -426,7 +434,7 @@ def main():
         "config": {"workload": case["desc"] + ", full KDK step" +
                    (", mixed precision" if mixed else ", FP64") +
                    (", replayed HIP graph" if graph else ""),
-                   "particles": case["n"], "bucket": head["bucket"],
+                   "particles": case["n"], "bucket": head["bucket"], "launch": head["launch"],
                    "schemes": schemes,
                    "parallelism": "single GPU"},
         "fp64": {k: results["fp64"].get(k) for k in ("pairs_per_s", "ms_per_step", "metric_rate",

@@ -164,10 +164,21 @@ typedef struct {
                           uniform body). */
     int32_t rung_max;  /* SPH_FLAG_RUNGS: finest rung, 0..20 (time is counted in units of
                           dt_max 2^-rung_max).  Default 8. */
-    int32_t reserved2_;
+    int32_t launch;    /* launch shape of the density and force sweeps:
+                          SPH_LAUNCH_GROUPS: one workgroup (one wavefront) per sink group;
+                          SPH_LAUNCH_PERSISTENT: as many workgroups as the GPU holds at
+                            once, each taking sink groups from per-XCD queues until none
+                            is left (each XCD's queue is one contiguous run of groups; an
+                            XCD that runs dry takes from the next).
+                          Results do not depend on it, only the cost; sph_autotune picks
+                          one.  Not combined with SPH_FLAG_RUNGS (its substeps launch one
+                          workgroup per group of the sink list); sph_init_noalloc always
+                          launches one workgroup per group.  Default SPH_LAUNCH_GROUPS. */
     double fastgas;    /* SPH_FLAG_RUNGS: active fraction below which the density pass is
                           restricted (0 = never).  Default 0. */
 } sph_params;
+
+enum { SPH_LAUNCH_GROUPS = 0, SPH_LAUNCH_PERSISTENT = 1 };
 
 enum {
     SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4, SPH_FLAG_DYNAMIC = 8,
@@ -242,6 +253,9 @@ typedef struct {
     int64_t n_fastgas_miss;       /* force-set neighbours of active particles that FastGas
                                      left out of the density pass (their density is that
                                      of an earlier substep) */
+    int64_t launch;               /* SPH_LAUNCH_* of the last call's sweeps */
+    int64_t workgroups_force;     /* workgroups of the last force launch (sink groups, or
+                                     the resident grid of a persistent launch) */
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -319,9 +333,13 @@ sph_status sph_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream);
 sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, void *stream);
 sph_status sph_graph_launch(sph_ctx *ctx, void *stream);
 
-/* Picks the bucket size by timing the density and force passes on the given
- * particles (synchronises; leaves H, rho, omega, P, c, a, dudt, dt written as
- * by sph_init).  The choice is kept in the context; returns it in *bucket. */
+/* Picks the bucket size (8, 16, 32, 64) and the sweeps' launch shape
+ * (SPH_LAUNCH_*; one workgroup per group only with SPH_FLAG_RUNGS) by timing
+ * the density and force passes of sph_init for every combination on the given
+ * particles, each from the same first guess of H (synchronises; leaves H, rho,
+ * omega, P, c, a, dudt, dt written as by sph_init).  The choice is kept in the
+ * context; returns the bucket size in *bucket and the launch shape in
+ * sph_stats.launch. */
 sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *stream);
 
 /* Turns device-side phase timing on (1) or off (0); timings appear in sph_stats.

@@ -45,11 +45,13 @@ class Params(ctypes.Structure):
         ("h_max", c_double), ("oversel", c_double), ("nr_tol", c_double),
         ("nr_maxit", c_int32), ("bucket", c_int32), ("stack_limit", c_int32),
         ("flags", c_int32), ("ic_alpha", c_double),
-        ("rung_max", c_int32), ("reserved2_", c_int32), ("fastgas", c_double),
+        ("rung_max", c_int32), ("launch", c_int32), ("fastgas", c_double),
     ]
 
 
 FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE, FLAG_DYNAMIC, FLAG_RUNGS = 1, 2, 4, 8, 16
+LAUNCH_GROUPS, LAUNCH_PERSISTENT = 0, 1
+LAUNCH_NAMES = {"groups": LAUNCH_GROUPS, "persistent": LAUNCH_PERSISTENT}
 
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H",
@@ -74,7 +76,7 @@ class Stats(ctypes.Structure):
         ("n_retest", c_int64), ("status", c_int32), ("reserved_", c_int32),
         ("slots_density", c_int64), ("slots_force", c_int64), ("groups_by_level", c_int64 * 4),
         ("t_units", c_int64), ("n_active", c_int64), ("n_dens", c_int64),
-        ("n_fastgas_miss", c_int64),
+        ("n_fastgas_miss", c_int64), ("launch", c_int64), ("workgroups_force", c_int64),
     ]
 
 
@@ -150,6 +152,9 @@ def make_params(p: dict) -> Params:
     for name in ("nr_maxit", "bucket", "stack_limit", "rung_max"):
         if name in p:
             setattr(q, name, int(p[name]))
+    if "launch" in p:
+        v = p["launch"]
+        q.launch = LAUNCH_NAMES[v] if isinstance(v, str) else int(v)
     q.flags = ((FLAG_ENTROPY if p.get("entropy") else 0) | (FLAG_EVOLVED if p.get("evolved") else 0)
                | (FLAG_INTERFACE if p.get("interface") else 0)
                | (FLAG_DYNAMIC if p.get("dynamic") else 0)

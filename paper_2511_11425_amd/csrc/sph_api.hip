@@ -63,6 +63,7 @@ void free_all(Ctx &c) {
     c.rho_old = c.rho_pred = c.rho_sum = c.drs = nullptr;
     c.mats = c.imbs = c.tbar = c.pbar = nullptr;
     c.levc = c.levs = c.d_levref = nullptr;
+    c.d_queue = nullptr;
     c.d_rung = nullptr; c.rungs = c.nbmax = c.nbmax_c = nullptr; c.rpack = nullptr;
     c.rflags = nullptr; c.sinks = c.dsinks = c.mark = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
@@ -111,6 +112,12 @@ bool valid_params(const sph_params *p, std::string &why) {
     if ((p->flags & SPH_FLAG_ENTROPY) && (p->flags & SPH_FLAG_EVOLVED)) {
         why = "the entropy-conserving update needs the summed density (not SPH_FLAG_EVOLVED)";
         return false;
+    }
+    if (p->launch != SPH_LAUNCH_GROUPS && p->launch != SPH_LAUNCH_PERSISTENT) {
+        why = "launch must be SPH_LAUNCH_GROUPS or SPH_LAUNCH_PERSISTENT"; return false;
+    }
+    if ((p->flags & SPH_FLAG_RUNGS) && p->launch != SPH_LAUNCH_GROUPS) {
+        why = "SPH_FLAG_RUNGS launches one workgroup per sink group"; return false;
     }
     if (p->flags & SPH_FLAG_RUNGS) {
         if (p->flags != SPH_FLAG_RUNGS) {
@@ -290,6 +297,7 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
         if (c.prm.fastgas > 0.0) A(c.mark, n + 2);
     }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
+    A(c.d_queue, kXcds * kQueueStride);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, kCntShards * kCntStride);
     A(c.d_csum, C_NCOUNTERS);
@@ -714,6 +722,10 @@ sph_status sph_create_batch(const sph_params *params, int32_t nsets, const int64
     c.base_bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
     c.bucket = c.dyn ? 8 : c.base_bucket;   // (dynamic sizing: the tree's buckets are the finest)
     if (c.prm.stack_limit == 0) c.prm.stack_limit = kStackCap;
+    c.launch = c.prm.launch;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&c.ncu, hipDeviceAttributeMultiprocessorCount, dev);
     c.nsets = nsets;
     if (set_offsets) c.set_off.assign(set_offsets, set_offsets + nsets + 1);
     if (set_box) c.set_box.assign(set_box, set_box + 6 * nsets);
@@ -968,6 +980,8 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
         out->n_dens = c.prm.fastgas > 0.0 ? rs.ndens : c.n;
         out->n_fastgas_miss = (int64_t)c.h_cnt[C_FGMISS];
     }
+    out->launch = c.sweep_launch;
+    out->workgroups_force = c.sweep_workgroups;
     c.status_pending = false;   // reported here, not again by the next call
     auto span = [&](int a, int b) -> double {
         if (!((c.ev_mask >> a) & 1u) || !((c.ev_mask >> b) & 1u)) return -1.0;
@@ -1016,12 +1030,18 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     st = sph_set_timing(ctx, 1);
     const int cands[4] = {8, 16, 32, 64};
     int best = c.dyn ? c.base_bucket : c.bucket;
+    int best_launch = c.launch;
     double tbest = 1e300;
-    for (int q = 0; q < 4 && st == SPH_OK && e == hipSuccess; ++q) {
+    // every bucket size with every launch shape (substeps of individual time
+    // steps launch one workgroup per group only)
+    const int nlaunch = c.rungs_on ? 1 : 2;
+    for (int q = 0; q < 4 * nlaunch && st == SPH_OK && e == hipSuccess; ++q) {
         // (dynamic sizing: the tree keeps buckets of 8; the trials set the
         // level the groups start from)
-        if (c.dyn) c.base_bucket = cands[q];
-        else c.bucket = cands[q];
+        if (c.dyn) c.base_bucket = cands[q % 4];
+        else c.bucket = cands[q % 4];
+        c.launch = c.rungs_on ? SPH_LAUNCH_GROUPS
+                              : (q < 4 ? SPH_LAUNCH_GROUPS : SPH_LAUNCH_PERSISTENT);
         double t = 1e300;
         for (int rep = 0; rep < 2 && st == SPH_OK && e == hipSuccess; ++rep) {
             e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
@@ -1032,8 +1052,9 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
             if (st == SPH_OK && ss.t_density_ms >= 0 && ss.t_forces_ms >= 0)
                 t = std::min(t, ss.t_density_ms + ss.t_forces_ms);
         }
-        if (t < tbest) { tbest = t; best = cands[q]; }
+        if (t < tbest) { tbest = t; best = cands[q % 4]; best_launch = c.launch; }
     }
+    c.launch = best_launch;
     if (st == SPH_OK && e == hipSuccess) {
         if (c.dyn) c.base_bucket = best;
         else c.bucket = best;
@@ -1075,6 +1096,7 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     c.dyn = (c.prm.flags & SPH_FLAG_DYNAMIC) != 0;
     c.base_bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
     c.bucket = c.dyn ? 8 : c.base_bucket;
+    c.launch = SPH_LAUNCH_GROUPS;   // (the static work space holds no queue)
     c.nsets = 1;
     c.timing = false;
     c.capturing = false;

@@ -50,6 +50,10 @@ inline int base_level(int bucket) {
 // the summary block the host reads (maximum for C_NR_ITER_MAX).
 constexpr int kCntShards = 16;
 constexpr int kCntStride = 32;   // 64-bit counters per copy
+// Workgroups are dealt to the XCDs in turn; the persistent sweep launch keeps
+// one queue counter per XCD, each on its own 256-byte line
+constexpr int kXcds = 8;
+constexpr int kQueueStride = 64;   // uint32 per queue counter
 static_assert(C_NCOUNTERS <= kCntStride, "counter copy too small");
 __host__ __device__ inline int64_t cnt_shard(int64_t g) { return (g % kCntShards) * kCntStride; }
 
@@ -175,6 +179,13 @@ struct Ctx {
     const long long *sweep_nsinks = nullptr;
     bool sweep_rpack = false;
     bool rpack_ready = false;   // sph_init: the desired rungs are packed (limiter pass)
+    // sweep launch shape (SPH_LAUNCH_*), the persistent launch's per-XCD queue
+    // counters, the device's CUs; shape and workgroups of the last force launch
+    int32_t launch = SPH_LAUNCH_GROUPS;
+    uint32_t *d_queue = nullptr;
+    int32_t ncu = 0;
+    int32_t sweep_launch = SPH_LAUNCH_GROUPS;
+    int64_t sweep_workgroups = 0;
     bool mats_has = false;     // the caller gave material ids
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
 

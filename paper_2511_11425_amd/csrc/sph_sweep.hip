@@ -496,11 +496,36 @@ __device__ __forceinline__ double bits_to_real(unsigned long long b) {
 // Hilbert curve, so neighbouring groups share most of their candidates; this
 // permutation gives every XCD one contiguous range of groups, so those shared
 // candidates are fetched into one L2 instead of eight.
-constexpr int kXcds = 8;
 __device__ __forceinline__ int64_t xcd_group(int64_t b, int64_t n) {
     const int64_t q = n / kXcds, r = n % kXcds;
     const int64_t x = b % kXcds, k = b / kXcds;
     return x * q + (x < r ? x : r) + k;
+}
+
+// Persistent launch: as many workgroups as the CUs hold at once, each taking
+// sink groups until none is left.  The groups are split into the same kXcds
+// contiguous ranges that xcd_group deals out, one queue counter per range (on
+// its own 256-byte line); a wave takes the next group of its own XCD's range
+// and, once that is empty, of the following ranges in turn, so an XCD that
+// finishes early helps the others.  Returns -1 once every range is empty: each
+// call either returns a group or moves k on, so every wave exits after at
+// most ngroups + kXcds fetches.  The counters start at zero (cleared before
+// the launch).
+__device__ __forceinline__ int64_t next_group(uint32_t *queue, int64_t n, int &k) {
+    const int x0 = (int)(blockIdx.x % kXcds);
+    const int64_t q = n / kXcds, r = n % kXcds;
+    while (k < kXcds) {
+        const int x = (x0 + k) % kXcds;
+        const int64_t len = q + (x < r ? 1 : 0);
+        uint32_t t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(&queue[x * kQueueStride], 1u);
+        // (all 64 lanes are active here: lane 0's value, as a scalar, so that
+        // the group index and all that follows from it stay in SGPRs)
+        t = __builtin_amdgcn_readfirstlane(t);
+        if ((int64_t)t < len) return x * q + (x < r ? x : r) + (int64_t)t;
+        ++k;
+    }
+    return -1;
 }
 
 struct SweepArgs {
@@ -549,6 +574,10 @@ struct SweepArgs {
     double *nbmax;
     uint32_t *mark;
     double fastgas;         // active fraction below which FastGas marks
+    // persistent launch: per-XCD queue counters (null: one workgroup per
+    // sink group) and the number of sink groups
+    uint32_t *queue;
+    int64_t ngroups;
 };
 
 // The sinks of group grp: sorted indices i (one per lane) and whether the
@@ -951,7 +980,7 @@ __device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const do
 // latency the extra waves hide (measured at 2M: mixed 2.48 ms at three
 // waves, 2.21 at four, 2.13 at five; FP64 7.29 at three, 6.83 at four).
 template <int K, bool MIXED>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4))) void k_density(SweepArgs a) {
+__device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
@@ -975,7 +1004,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     __shared__ double acc0[kWave], acc1[kWave], acc2[kWave];
 
     const int lane = threadIdx.x;
-    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     unsigned long long *const ctr = a.cnt + cnt_shard(grp);   // this group's counter copy
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
@@ -1328,6 +1356,19 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
     }
 }
 
+// One workgroup (one wave) per sink group, or (PERSIST) a resident grid
+// taking groups from the per-XCD queues.
+template <int K, bool MIXED, bool PERSIST>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4))) void k_density(SweepArgs a) {
+    if constexpr (PERSIST) {
+        int k = 0;
+        for (int64_t grp; (grp = next_group(a.queue, a.ngroups, k)) >= 0;)
+            density_group<K, MIXED>(a, grp);
+    } else {
+        density_group<K, MIXED>(a, xcd_group(blockIdx.x, gridDim.x));
+    }
+}
+
 // ================================================================ forces
 
 // Occupancy of the force kernels.  Their walk stack lives in global memory
@@ -1337,7 +1378,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // values spilled to scratch) cost more than it hid (2M mixed forces 3.81 ms
 // at four waves, 3.24 at three).
 template <int K, bool MIXED, bool RUNGS>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_forces(SweepArgs a) {
+__device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
@@ -1374,7 +1415,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
     __shared__ int armax[RUNGS ? kWave : 1], asidx[RUNGS ? kWave : 1], amiss[1];
 
     const int lane = threadIdx.x;
-    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
     unsigned long long *const ctr = a.cnt + cnt_shard(grp);   // this group's counter copy
     uint32_t *const stack = a.wstack + grp * kStackCap;
     const int sid = a.grp_set[grp];
@@ -1741,6 +1781,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void
         atomicAdd(&ctr[C_PAIRS_F_TOT], (unsigned long long)pairs_n);
         atomicAdd(&ctr[C_CAND_F], cand_tested * (unsigned long long)nact);
         if (overflows) atomicAdd(&ctr[C_OVERFLOW], (unsigned long long)overflows);
+    }
+}
+
+template <int K, bool MIXED, bool RUNGS, bool PERSIST>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_forces(SweepArgs a) {
+    if constexpr (PERSIST) {
+        int k = 0;
+        for (int64_t grp; (grp = next_group(a.queue, a.ngroups, k)) >= 0;)
+            forces_group<K, MIXED, RUNGS>(a, grp);
+    } else {
+        forces_group<K, MIXED, RUNGS>(a, xcd_group(blockIdx.x, gridDim.x));
     }
 }
 
@@ -2155,35 +2206,89 @@ inline SweepArgs base_args(Ctx *c) {
     return a;
 }
 
+// Clears the persistent launch's queue counters (a kernel rather than a
+// memset, so the clear can be captured in a graph).
+__global__ void k_queue_reset(uint32_t *queue) {
+    if (threadIdx.x < kXcds) queue[threadIdx.x * kQueueStride] = 0u;
+}
+
+// Workgroups of a persistent launch: what the CUs hold at once (occupancy
+// from the kernel's registers and LDS), at most one per sink group.  The
+// count is taken once per kernel instance.
+template <typename F>
+unsigned persistent_grid(Ctx *c, F kernel, int &cache) {
+    if (cache <= 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cache = per_cu;
+    }
+    const int64_t cap = c->ncu > 0 ? (int64_t)cache * c->ncu : c->ngroups;
+    return (unsigned)(c->ngroups < cap ? c->ngroups : cap);
+}
+
+template <int K, bool MIXED>
+void launch_density_k(Ctx *c, SweepArgs &a, hipStream_t s) {
+    if (a.queue) {
+        static int occ = 0;
+        const unsigned grid = persistent_grid(c, k_density<K, MIXED, true>, occ);
+        k_density<K, MIXED, true><<<grid, kWave, 0, s>>>(a);
+    } else {
+        k_density<K, MIXED, false><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+    }
+}
+
+template <int K, bool MIXED>
+void launch_forces_k(Ctx *c, SweepArgs &a, hipStream_t s) {
+    if (a.rpack) {
+        // (individual time steps: one workgroup per group of the sink list)
+        c->sweep_workgroups = c->ngroups;
+        c->sweep_launch = SPH_LAUNCH_GROUPS;
+        k_forces<K, MIXED, true, false><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+    } else if (a.queue) {
+        static int occ = 0;
+        const unsigned grid = persistent_grid(c, k_forces<K, MIXED, false, true>, occ);
+        c->sweep_workgroups = grid;
+        c->sweep_launch = SPH_LAUNCH_PERSISTENT;
+        k_forces<K, MIXED, false, true><<<grid, kWave, 0, s>>>(a);
+    } else {
+        c->sweep_workgroups = c->ngroups;
+        c->sweep_launch = SPH_LAUNCH_GROUPS;
+        k_forces<K, MIXED, false, false><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+    }
+}
+
+// The launch shape of the context: a persistent launch clears its queue
+// counters first.
+inline hipError_t set_launch(Ctx *c, SweepArgs &a, bool rungs, hipStream_t s) {
+    a.ngroups = c->ngroups;
+    a.queue = (c->launch == SPH_LAUNCH_PERSISTENT && c->d_queue && !rungs) ? c->d_queue : nullptr;
+    if (a.queue) {
+        k_queue_reset<<<1, kWave, 0, s>>>(a.queue);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
 template <bool MIXED>
 hipError_t density_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
-    dim3 grid((unsigned)c->ngroups), block(kWave);
     switch (c->prm.kernel) {
-    case 0: k_density<0, MIXED><<<grid, block, 0, s>>>(a); break;
-    case 1: k_density<1, MIXED><<<grid, block, 0, s>>>(a); break;
-    case 2: k_density<2, MIXED><<<grid, block, 0, s>>>(a); break;
-    default: k_density<3, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 0: launch_density_k<0, MIXED>(c, a, s); break;
+    case 1: launch_density_k<1, MIXED>(c, a, s); break;
+    case 2: launch_density_k<2, MIXED>(c, a, s); break;
+    default: launch_density_k<3, MIXED>(c, a, s); break;
     }
     return hipGetLastError();
 }
 
 template <bool MIXED>
 hipError_t forces_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
-    dim3 grid((unsigned)c->ngroups), block(kWave);
-    if (a.rpack) {
-        switch (c->prm.kernel) {
-        case 0: k_forces<0, MIXED, true><<<grid, block, 0, s>>>(a); break;
-        case 1: k_forces<1, MIXED, true><<<grid, block, 0, s>>>(a); break;
-        case 2: k_forces<2, MIXED, true><<<grid, block, 0, s>>>(a); break;
-        default: k_forces<3, MIXED, true><<<grid, block, 0, s>>>(a); break;
-        }
-        return hipGetLastError();
-    }
     switch (c->prm.kernel) {
-    case 0: k_forces<0, MIXED, false><<<grid, block, 0, s>>>(a); break;
-    case 1: k_forces<1, MIXED, false><<<grid, block, 0, s>>>(a); break;
-    case 2: k_forces<2, MIXED, false><<<grid, block, 0, s>>>(a); break;
-    default: k_forces<3, MIXED, false><<<grid, block, 0, s>>>(a); break;
+    case 0: launch_forces_k<0, MIXED>(c, a, s); break;
+    case 1: launch_forces_k<1, MIXED>(c, a, s); break;
+    case 2: launch_forces_k<2, MIXED>(c, a, s); break;
+    default: launch_forces_k<3, MIXED>(c, a, s); break;
     }
     return hipGetLastError();
 }
@@ -2193,9 +2298,11 @@ hipError_t forces_dispatch(Ctx *c, SweepArgs a, hipStream_t s) {
 hipError_t launch_density(Ctx *c, hipStream_t s) {
     if (c->ngroups == 0) return hipSuccess;
     SweepArgs a = base_args(c);
+    hipError_t e = set_launch(c, a, c->sweep_sinks != nullptr, s);
+    if (e != hipSuccess) return e;
     mark(c, E_DEN0, s);
-    hipError_t e = c->prm.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, a, s)
-                                                      : density_dispatch<false>(c, a, s);
+    e = c->prm.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, a, s)
+                                           : density_dispatch<false>(c, a, s);
     mark(c, E_DEN1, s);
     return e;
 }
@@ -2220,9 +2327,11 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
     a.ax = c->axs; a.ay = c->ays; a.az = c->azs; a.du = c->dus; a.dt = c->dts;
     a.drho = (c->prm.flags & SPH_FLAG_EVOLVED) ? c->drs : nullptr;
     a.entropy = (c->prm.flags & SPH_FLAG_ENTROPY) ? 1 : 0;
+    hipError_t e = set_launch(c, a, a.rpack != nullptr, s);
+    if (e != hipSuccess) return e;
     mark(c, E_FOR0, s);
-    hipError_t e = c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
-                                                      : forces_dispatch<false>(c, a, s);
+    e = c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
+                                           : forces_dispatch<false>(c, a, s);
     mark(c, E_FOR1, s);
     if (e == hipSuccess && c->dyn) {
         k_level_ref<<<1, 64, 0, s>>>(c->d_cnt, c->ngroups, c->n, c->d_levref);
