@@ -256,6 +256,9 @@ typedef struct {
     int64_t launch;               /* SPH_LAUNCH_* of the last call's sweeps */
     int64_t workgroups_force;     /* workgroups of the last force launch (sink groups, or
                                      the resident grid of a persistent launch) */
+    double t_force_walk_ms;       /* with timing on: device time of the force pass's tree
+                                     walk (a kernel of its own, before the force kernel,
+                                     whose time is t_forces_ms); -1 when it did not run */
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */

@@ -77,6 +77,7 @@ class Stats(ctypes.Structure):
         ("slots_density", c_int64), ("slots_force", c_int64), ("groups_by_level", c_int64 * 4),
         ("t_units", c_int64), ("n_active", c_int64), ("n_dens", c_int64),
         ("n_fastgas_miss", c_int64), ("launch", c_int64), ("workgroups_force", c_int64),
+        ("t_force_walk_ms", c_double),
     ]
 
 

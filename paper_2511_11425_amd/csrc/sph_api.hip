@@ -64,6 +64,7 @@ void free_all(Ctx &c) {
     c.mats = c.imbs = c.tbar = c.pbar = nullptr;
     c.levc = c.levs = c.d_levref = nullptr;
     c.d_queue = nullptr;
+    c.d_glist = nullptr; c.d_gws = nullptr;
     c.d_rung = nullptr; c.rungs = c.nbmax = c.nbmax_c = nullptr; c.rpack = nullptr;
     c.rflags = nullptr; c.sinks = c.dsinks = c.mark = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
@@ -297,6 +298,8 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
         if (c.prm.fastgas > 0.0) A(c.mark, n + 2);
     }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
+    A(c.d_glist, (size_t)std::max<int64_t>(c.ngroups, 1) * kCandCap);
+    A(c.d_gws, (size_t)std::max<int64_t>(c.ngroups, 1) * kWalkWords);
     A(c.d_queue, kXcds * kQueueStride);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, kCntShards * kCntStride);
@@ -992,6 +995,7 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->t_tree_ms = span(E_TREE0, E_TREE1);
     out->t_density_ms = span(E_DEN0, E_DEN1);
     out->t_forces_ms = span(E_FOR0, E_FOR1);
+    out->t_force_walk_ms = span(E_FWALK0, E_FOR0);
     out->t_total_ms = span(E_BEGIN, E_END);
     return SPH_OK;
 }

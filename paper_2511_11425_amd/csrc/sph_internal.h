@@ -54,11 +54,14 @@ constexpr int kCntStride = 32;   // 64-bit counters per copy
 // one queue counter per XCD, each on its own 256-byte line
 constexpr int kXcds = 8;
 constexpr int kQueueStride = 64;   // uint32 per queue counter
+constexpr int kWalkWords = 8;      // int32 per stored walk state
 static_assert(C_NCOUNTERS <= kCntStride, "counter copy too small");
 __host__ __device__ inline int64_t cnt_shard(int64_t g) { return (g % kCntShards) * kCntStride; }
 
 // Timing events recorded around the phases when timing is on.
-enum TimingEvent { E_BEGIN = 0, E_TREE0, E_TREE1, E_DEN0, E_DEN1, E_FOR0, E_FOR1, E_END, E_NEVENTS };
+enum TimingEvent {
+    E_BEGIN = 0, E_TREE0, E_TREE1, E_DEN0, E_DEN1, E_FWALK0, E_FOR0, E_FOR1, E_END, E_NEVENTS
+};
 
 // FP64 results of the last step (device), copied into sph_stats.
 struct StepReport {
@@ -188,6 +191,11 @@ struct Ctx {
     int64_t sweep_workgroups = 0;
     bool mats_has = false;     // the caller gave material ids
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
+    // the force pass's walk, run before the force kernel: refined candidate
+    // buckets (kCandCap per sink group) and walk state (kWalkWords per group);
+    // null: the force kernel walks itself
+    uint32_t *d_glist = nullptr;
+    int32_t *d_gws = nullptr;
 
     // scan scratch
     int64_t *d_scan_tmp = nullptr;

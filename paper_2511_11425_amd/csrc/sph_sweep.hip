@@ -578,6 +578,11 @@ struct SweepArgs {
     // sink group) and the number of sink groups
     uint32_t *queue;
     int64_t ngroups;
+    // force pass: each group's walk and refinement done by k_walk_force
+    // (candidate buckets, kCandCap per group; walk state, kWalkWords per
+    // group); null: the force kernel walks itself
+    uint32_t *glist;
+    int32_t *gws;
 };
 
 // The sinks of group grp: sorted indices i (one per lane) and whether the
@@ -1377,6 +1382,54 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // distance tests, the fourth wave of the mixed kernel (128 VGPRs, 52 of its
 // values spilled to scratch) cost more than it hid (2M mixed forces 3.81 ms
 // at four waves, 3.24 at three).
+// The force pass's walk and refinement of each sink group, as a kernel of its
+// own before the force kernel: each step of the walk waits on memory, and at
+// this kernel's occupancy (84 VGPRs, five waves per SIMD, against the force
+// kernel's three) the waits of more groups overlap.  The refined candidate
+// buckets and the walk state go to global memory; the walk stack stays where
+// it is, so a group whose list does not fit continues the walk in the force
+// kernel.  The same code and inputs as the force kernel's own walk, hence
+// the same list.
+__global__ __launch_bounds__(kWave) void k_walk_force(SweepArgs a) {
+    __shared__ uint32_t cand[kCandCap];
+    __shared__ alignas(16) float stage[kRefineStageBytes / 4];
+    const int lane = threadIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    uint32_t *const stack = a.wstack + grp * kStackCap;
+    const int sid = a.grp_set[grp];
+    SetGeom g = a.sets[sid];
+    const bool per = a.periodic != 0;
+    const double slop = set_slop(g);
+    int64_t i;
+    bool act;
+    if (!group_sinks(a, g, grp, i, act)) return;
+    int level;
+    (void)group_bucket(a, g, i, act, level);
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    const double Hd = act ? a.Hs[i] : 0.0;
+    double gc[3];
+    for (int q = 0; q < 3; ++q) {
+        double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
+        gc[q] = 0.5 * (mn + mx);
+    }
+    double gext[3];
+    for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
+    const double Hsink_max = wave_max(act ? Hd : 0.0);
+    Sink sk;
+    sink_bounds(act, xi, Hd, sk);
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
+    walk_reset(stack, ws, false, g);
+    walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+    if (!ws.overflow)
+        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
+    for (int t = lane; t < ws.ncand; t += kWave) a.glist[grp * kCandCap + t] = cand[t];
+    if (lane == 0) {
+        int32_t *w = a.gws + grp * kWalkWords;
+        w[0] = ws.nstack; w[1] = ws.ncand; w[2] = ws.lin; w[3] = ws.cap;
+        w[4] = ws.overflow ? 1 : 0; w[5] = ws.far ? 1 : 0;
+    }
+}
+
 template <int K, bool MIXED, bool RUNGS>
 __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
@@ -1500,10 +1553,22 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     int retests = 0;   // pairs the wave re-tested in FP64
     unsigned long long cand_tested = 0;
     unsigned long long slots = 0;   // candidate slots loaded (before the filter)
-    walk_reset(stack, ws, linear, g);
+    // the first part of the list (and the stack, where the walk continues)
+    // comes from k_walk_force when it ran, already refined
+    bool pre = a.glist != nullptr, refined = pre;
+    if (!pre) walk_reset(stack, ws, linear, g);
 
     while (true) {
-        walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        if (pre) {
+            pre = false;
+            const int32_t *w = a.gws + grp * kWalkWords;
+            ws.nstack = w[0]; ws.ncand = w[1]; ws.lin = w[2]; ws.cap = w[3];
+            ws.overflow = w[4] != 0; ws.far = w[5] != 0;
+            for (int t = lane; t < ws.ncand; t += kWave) cand[t] = a.glist[grp * kCandCap + t];
+            __syncthreads();
+        } else {
+            walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        }
         if (ws.overflow) {
             // restart the whole pass with the linear bucket test
             ++overflows;
@@ -1515,10 +1580,13 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
             cand_tested = 0;
             slots = 0;
             amu[lane] = 0;
+            refined = false;
             walk_reset(stack, ws, true, g);
             continue;
         }
-        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
+        if (!refined)
+            refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
+        refined = false;
         const int nload = sweep_tiles(ws.ncand, Bg);
         int qb = 0, qn = 0;   // candidate queue: first entry, entries
         // One tile: the 64 queue entries from qb (nv of them valid).
@@ -2329,6 +2397,14 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
     a.entropy = (c->prm.flags & SPH_FLAG_ENTROPY) ? 1 : 0;
     hipError_t e = set_launch(c, a, a.rpack != nullptr, s);
     if (e != hipSuccess) return e;
+    if (c->d_glist) {
+        a.glist = c->d_glist;
+        a.gws = c->d_gws;
+        mark(c, E_FWALK0, s);
+        k_walk_force<<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     mark(c, E_FOR0, s);
     e = c->prm.precision == SPH_PREC_MIXED ? forces_dispatch<true>(c, a, s)
                                            : forces_dispatch<false>(c, a, s);
