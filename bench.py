@@ -185,7 +185,8 @@ def run_gpu(case, precision, steps, warmup, graph=False):
         "n_overflow": st["n_overflow"],
         "slots_density": st["slots_density"], "slots_force": st["slots_force"],
         "groups_by_level": list(st["groups_by_level"]),
-        "launch": "persistent" if st["launch"] == sph.LAUNCH_PERSISTENT else "groups",
+        "launch": {sph.LAUNCH_GROUPS: "groups", sph.LAUNCH_PERSISTENT: "persistent",
+                   sph.LAUNCH_WALK: "walk"}[st["launch"]],
         "workgroups_force": st["workgroups_force"],
     }
     if tden:
@@ -352,7 +353,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="replay one captured step as a HIP graph")
     ap.add_argument("--bucket", type=int, default=0,
                     help="bucket size 8, 16, 32 or 64 (default: the workload's)")
-    ap.add_argument("--launch", default="", choices=["", "groups", "persistent"],
+    ap.add_argument("--launch", default="", choices=["", "groups", "persistent", "walk"],
                     help="sweep launch shape (default: the autotuner's choice)")
     ap.add_argument("--scheme", default="",
                     help="comma list of optional schemes: " + ",".join(SCHEMES))
@@ -405,9 +406,10 @@ def main():
             flops = head["pairs_density"] * FLOP_DENSITY_PAIR * head["nr_scans_mean"]
             t = head["t_density_ms"] * 1e-3
         kidx = KERNEL_INDEX[case["params"].get("kernel", "m4")]
-        persist = "true" if head["launch"] == "persistent" else "false"
+        # (kernel template: ..., launch mode 0 walking, 1 listed, 2 listed persistent)
+        lm = {"walk": 0, "groups": 1, "persistent": 2}[head["launch"]]
         kname = f"k_{dom}<{kidx}, {'true' if mixed else 'false'}" + \
-            (f", false, {persist}>" if dom == "forces" else f", {persist}>")   # (forces: no rung maximum)
+            (f", false, {lm}>" if dom == "forces" else f", {lm}>")   # (forces: no rung maximum)
         achieved = flops / t
         roof = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                 "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],

@@ -164,21 +164,28 @@ typedef struct {
                           uniform body). */
     int32_t rung_max;  /* SPH_FLAG_RUNGS: finest rung, 0..20 (time is counted in units of
                           dt_max 2^-rung_max).  Default 8. */
-    int32_t launch;    /* launch shape of the density and force sweeps:
+    int32_t launch;    /* launch shape of the density and force sweeps.  The first two
+                          take each sink group's interaction list from a walk kernel
+                          run before the sweep (stored in the context, up to 1024
+                          buckets per group; a longer list, or in the density pass a
+                          root beyond the stored list's radius, sends the group to a
+                          sweep kernel that walks the tree itself):
                           SPH_LAUNCH_GROUPS: one workgroup (one wavefront) per sink group;
                           SPH_LAUNCH_PERSISTENT: as many workgroups as the GPU holds at
                             once, each taking sink groups from per-XCD queues until none
                             is left (each XCD's queue is one contiguous run of groups; an
-                            XCD that runs dry takes from the next).
+                            XCD that runs dry takes from the next);
+                          SPH_LAUNCH_WALK: one workgroup per sink group, each walking the
+                            tree itself (no stored lists).
                           Results do not depend on it, only the cost; sph_autotune picks
-                          one.  Not combined with SPH_FLAG_RUNGS (its substeps launch one
-                          workgroup per group of the sink list); sph_init_noalloc always
-                          launches one workgroup per group.  Default SPH_LAUNCH_GROUPS. */
+                          one.  SPH_FLAG_RUNGS takes SPH_LAUNCH_GROUPS only, and its
+                          substeps walk in the sweep kernels; sph_init_noalloc walks in the
+                          sweep kernels.  Default SPH_LAUNCH_GROUPS. */
     double fastgas;    /* SPH_FLAG_RUNGS: active fraction below which the density pass is
                           restricted (0 = never).  Default 0. */
 } sph_params;
 
-enum { SPH_LAUNCH_GROUPS = 0, SPH_LAUNCH_PERSISTENT = 1 };
+enum { SPH_LAUNCH_GROUPS = 0, SPH_LAUNCH_PERSISTENT = 1, SPH_LAUNCH_WALK = 2 };
 
 enum {
     SPH_FLAG_ENTROPY = 1, SPH_FLAG_EVOLVED = 2, SPH_FLAG_INTERFACE = 4, SPH_FLAG_DYNAMIC = 8,
@@ -256,9 +263,14 @@ typedef struct {
     int64_t launch;               /* SPH_LAUNCH_* of the last call's sweeps */
     int64_t workgroups_force;     /* workgroups of the last force launch (sink groups, or
                                      the resident grid of a persistent launch) */
-    double t_force_walk_ms;       /* with timing on: device time of the force pass's tree
-                                     walk (a kernel of its own, before the force kernel,
-                                     whose time is t_forces_ms); -1 when it did not run */
+    double t_force_walk_ms;       /* with timing on: device time of the force pass's and */
+    double t_density_walk_ms;     /* the density pass's tree walks (kernels of their own,
+                                     before the sweep kernels, whose times are t_forces_ms
+                                     and t_density_ms); -1 when they did not run */
+    int64_t groups_walked;        /* sink groups of the last call whose interaction list
+                                     was too long to store (or, in the density pass, whose
+                                     root lay beyond the stored list): swept again from the
+                                     start by the kernel that walks the tree itself */
 } sph_stats;
 
 /* Fills *p with the defaults listed above. */

@@ -50,8 +50,8 @@ class Params(ctypes.Structure):
 
 
 FLAG_ENTROPY, FLAG_EVOLVED, FLAG_INTERFACE, FLAG_DYNAMIC, FLAG_RUNGS = 1, 2, 4, 8, 16
-LAUNCH_GROUPS, LAUNCH_PERSISTENT = 0, 1
-LAUNCH_NAMES = {"groups": LAUNCH_GROUPS, "persistent": LAUNCH_PERSISTENT}
+LAUNCH_GROUPS, LAUNCH_PERSISTENT, LAUNCH_WALK = 0, 1, 2
+LAUNCH_NAMES = {"groups": LAUNCH_GROUPS, "persistent": LAUNCH_PERSISTENT, "walk": LAUNCH_WALK}
 
 
 FIELDS = ("x", "y", "z", "vx", "vy", "vz", "m", "u", "H",
@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
         ("slots_density", c_int64), ("slots_force", c_int64), ("groups_by_level", c_int64 * 4),
         ("t_units", c_int64), ("n_active", c_int64), ("n_dens", c_int64),
         ("n_fastgas_miss", c_int64), ("launch", c_int64), ("workgroups_force", c_int64),
-        ("t_force_walk_ms", c_double),
+        ("t_force_walk_ms", c_double), ("t_density_walk_ms", c_double),
+        ("groups_walked", c_int64),
     ]
 
 

@@ -64,7 +64,7 @@ void free_all(Ctx &c) {
     c.mats = c.imbs = c.tbar = c.pbar = nullptr;
     c.levc = c.levs = c.d_levref = nullptr;
     c.d_queue = nullptr;
-    c.d_glist = nullptr; c.d_gws = nullptr;
+    c.d_wlist = nullptr; c.d_whdr = nullptr; c.d_defer = nullptr;
     c.d_rung = nullptr; c.rungs = c.nbmax = c.nbmax_c = nullptr; c.rpack = nullptr;
     c.rflags = nullptr; c.sinks = c.dsinks = c.mark = nullptr;
     if (c.h_cnt) { (void)hipHostFree(c.h_cnt); c.h_cnt = nullptr; }
@@ -114,8 +114,10 @@ bool valid_params(const sph_params *p, std::string &why) {
         why = "the entropy-conserving update needs the summed density (not SPH_FLAG_EVOLVED)";
         return false;
     }
-    if (p->launch != SPH_LAUNCH_GROUPS && p->launch != SPH_LAUNCH_PERSISTENT) {
-        why = "launch must be SPH_LAUNCH_GROUPS or SPH_LAUNCH_PERSISTENT"; return false;
+    if (p->launch != SPH_LAUNCH_GROUPS && p->launch != SPH_LAUNCH_PERSISTENT &&
+        p->launch != SPH_LAUNCH_WALK) {
+        why = "launch must be SPH_LAUNCH_GROUPS, SPH_LAUNCH_PERSISTENT or SPH_LAUNCH_WALK";
+        return false;
     }
     if ((p->flags & SPH_FLAG_RUNGS) && p->launch != SPH_LAUNCH_GROUPS) {
         why = "SPH_FLAG_RUNGS launches one workgroup per sink group"; return false;
@@ -298,8 +300,11 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
         if (c.prm.fastgas > 0.0) A(c.mark, n + 2);
     }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
-    A(c.d_glist, (size_t)std::max<int64_t>(c.ngroups, 1) * kCandCap);
-    A(c.d_gws, (size_t)std::max<int64_t>(c.ngroups, 1) * kWalkWords);
+    if (!c.rungs_on) {
+        A(c.d_wlist, (size_t)std::max<int64_t>(c.ngroups, 1) * kListCap);
+        A(c.d_whdr, (size_t)std::max<int64_t>(c.ngroups, 1) * kWalkWords);
+        A(c.d_defer, (size_t)std::max<int64_t>(c.ngroups, 1));
+    }
     A(c.d_queue, kXcds * kQueueStride);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, kCntShards * kCntStride);
@@ -996,6 +1001,8 @@ sph_status sph_get_stats(sph_ctx *ctx, sph_stats *out) {
     out->t_density_ms = span(E_DEN0, E_DEN1);
     out->t_forces_ms = span(E_FOR0, E_FOR1);
     out->t_force_walk_ms = span(E_FWALK0, E_FOR0);
+    out->t_density_walk_ms = span(E_DWALK0, E_DEN0);
+    out->groups_walked = (int64_t)c.h_cnt[C_WALKED];
     out->t_total_ms = span(E_BEGIN, E_END);
     return SPH_OK;
 }
@@ -1037,15 +1044,15 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     int best_launch = c.launch;
     double tbest = 1e300;
     // every bucket size with every launch shape (substeps of individual time
-    // steps launch one workgroup per group only)
-    const int nlaunch = c.rungs_on ? 1 : 2;
+    // steps launch one walking workgroup per group only)
+    const int shapes[3] = {SPH_LAUNCH_GROUPS, SPH_LAUNCH_PERSISTENT, SPH_LAUNCH_WALK};
+    const int nlaunch = c.rungs_on ? 1 : 3;
     for (int q = 0; q < 4 * nlaunch && st == SPH_OK && e == hipSuccess; ++q) {
         // (dynamic sizing: the tree keeps buckets of 8; the trials set the
         // level the groups start from)
         if (c.dyn) c.base_bucket = cands[q % 4];
         else c.bucket = cands[q % 4];
-        c.launch = c.rungs_on ? SPH_LAUNCH_GROUPS
-                              : (q < 4 ? SPH_LAUNCH_GROUPS : SPH_LAUNCH_PERSISTENT);
+        c.launch = c.rungs_on ? SPH_LAUNCH_GROUPS : shapes[q / 4];
         double t = 1e300;
         for (int rep = 0; rep < 2 && st == SPH_OK && e == hipSuccess; ++rep) {
             e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
@@ -1100,7 +1107,7 @@ sph_status sph_init_noalloc(const sph_params *params, sph_particles *p, int64_t 
     c.dyn = (c.prm.flags & SPH_FLAG_DYNAMIC) != 0;
     c.base_bucket = c.prm.bucket == 0 ? 32 : c.prm.bucket;
     c.bucket = c.dyn ? 8 : c.base_bucket;
-    c.launch = SPH_LAUNCH_GROUPS;   // (the static work space holds no queue)
+    c.launch = SPH_LAUNCH_WALK;   // (the static work space holds no queue and no lists)
     c.nsets = 1;
     c.timing = false;
     c.capturing = false;

@@ -29,6 +29,7 @@ enum Counter {
     C_SLOTS_D, C_SLOTS_F,                 // candidate slots loaded (interaction-list lengths)
     C_LEV0, C_LEV1, C_LEV2, C_LEV3,       // force-pass sink groups per bucket level
     C_FGMISS,                             // FastGas: force pairs with a stale neighbour density
+    C_WALKED,                             // sink groups left to the walking sweep kernels
     C_NTRANSIENT,                         // counters above are cleared by every call
     C_PAIRS_D_TOT = C_NTRANSIENT,         // running totals since the context was made
     C_PAIRS_F_TOT,
@@ -54,13 +55,22 @@ constexpr int kCntStride = 32;   // 64-bit counters per copy
 // one queue counter per XCD, each on its own 256-byte line
 constexpr int kXcds = 8;
 constexpr int kQueueStride = 64;   // uint32 per queue counter
-constexpr int kWalkWords = 8;      // int32 per stored walk state
+// Stored interaction lists (the walk kernels): up to kListChunks chunks of at
+// most kCandCap refined buckets per sink group, and a header of kWalkWords:
+// chunks, the bucket count of each chunk, the chunks' minimum-image flags (a
+// bit each), and kList* flags
+constexpr int kListChunks = 4;
+constexpr int kListCap = kListChunks * kCandCap;
+constexpr int kWalkWords = 8;
+constexpr int kListLong = 1;       // more than kListChunks chunks: not stored
+constexpr int kListLinear = 2;     // the walk outgrew its stack and ran as the linear test
 static_assert(C_NCOUNTERS <= kCntStride, "counter copy too small");
 __host__ __device__ inline int64_t cnt_shard(int64_t g) { return (g % kCntShards) * kCntStride; }
 
 // Timing events recorded around the phases when timing is on.
 enum TimingEvent {
-    E_BEGIN = 0, E_TREE0, E_TREE1, E_DEN0, E_DEN1, E_FWALK0, E_FOR0, E_FOR1, E_END, E_NEVENTS
+    E_BEGIN = 0, E_TREE0, E_TREE1, E_DWALK0, E_DEN0, E_DEN1, E_FWALK0, E_FOR0, E_FOR1, E_END,
+    E_NEVENTS
 };
 
 // FP64 results of the last step (device), copied into sph_stats.
@@ -191,11 +201,12 @@ struct Ctx {
     int64_t sweep_workgroups = 0;
     bool mats_has = false;     // the caller gave material ids
     uint32_t *d_wstack = nullptr;   // sweep walk stacks, kStackCap node ids per sink group
-    // the force pass's walk, run before the force kernel: refined candidate
-    // buckets (kCandCap per sink group) and walk state (kWalkWords per group);
-    // null: the force kernel walks itself
-    uint32_t *d_glist = nullptr;
-    int32_t *d_gws = nullptr;
+    // stored interaction lists of the sweeps (kListCap buckets and a header of
+    // kWalkWords per sink group; one pass at a time) and the per-group flag of
+    // the groups left to the walking kernels; null: the sweeps walk themselves
+    uint32_t *d_wlist = nullptr;
+    int32_t *d_whdr = nullptr;
+    int32_t *d_defer = nullptr;
 
     // scan scratch
     int64_t *d_scan_tmp = nullptr;

@@ -578,11 +578,14 @@ struct SweepArgs {
     // sink group) and the number of sink groups
     uint32_t *queue;
     int64_t ngroups;
-    // force pass: each group's walk and refinement done by k_walk_force
-    // (candidate buckets, kCandCap per group; walk state, kWalkWords per
-    // group); null: the force kernel walks itself
-    uint32_t *glist;
-    int32_t *gws;
+    // stored interaction lists (k_walk; kListCap buckets and a header of
+    // kWalkWords per group) and the flags of the groups left to the walking
+    // kernels (null in a walking launch: every group)
+    const uint32_t *wlist;
+    const int32_t *whdr;
+    int32_t *defer;
+    uint32_t *wlist_out;
+    int32_t *whdr_out;
 };
 
 // The sinks of group grp: sorted indices i (one per lane) and whether the
@@ -984,7 +987,7 @@ __device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const do
 // four waves.  The values that then spill to scratch cost less than the
 // latency the extra waves hide (measured at 2M: mixed 2.48 ms at three
 // waves, 2.21 at four, 2.13 at five; FP64 7.29 at three, 6.83 at four).
-template <int K, bool MIXED>
+template <int K, bool MIXED, bool LISTED>
 __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
@@ -1019,6 +1022,8 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
     int64_t i;
     bool act;
     if (!group_sinks(a, g, grp, i, act)) return;
+    // a walking launch after a listed one: only the groups it left
+    if (!LISTED && a.defer && a.defer[grp] == 0) return;
     int level;
     const int Bg = group_bucket(a, g, i, act, level);   // this group's bucket size
     const int lb = 31 - __builtin_clz((unsigned)Bg);     // Bg = 2^lb
@@ -1074,9 +1079,41 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
     unsigned long long cand_tested = 0;
     unsigned long long slots = 0;   // candidate slots loaded (before the filter)
     bool need_walk = true;
+    // LISTED: the list at Hw comes from k_walk in chunks; a list too long to
+    // store, or a root beyond Hw (a new walk), leaves the group to the
+    // walking kernel, which redoes it from the start
+    const int32_t *const hdr = LISTED ? a.whdr + grp * kWalkWords : nullptr;
+    int nch = 0, farm = 0;
+    auto load_chunk = [&](int c) {
+        ws.ncand = hdr[1 + c];
+        ws.far = ((farm >> c) & 1) != 0;
+        const uint32_t *src = a.wlist + grp * kListCap + c * kCandCap;
+        for (int t = lane; t < ws.ncand; t += kWave) cand[t] = src[t];
+        __syncthreads();
+    };
+    auto defer_group = [&]() {
+        if (lane == 0) {
+            a.defer[grp] = 1;
+            atomicAdd(&ctr[C_WALKED], 1ull);
+        }
+    };
 
     while (true) {
-        if (need_walk) {
+        if (need_walk && LISTED) {
+            const int flags = hdr[6];
+            if (flags & kListLong) { defer_group(); return; }
+            if (lane == 0) a.defer[grp] = 0;
+            if (flags & kListLinear) ++overflows;
+            nch = hdr[0];
+            farm = hdr[5];
+            list_complete = nch <= 1;
+            ws.ncand = 0;
+            ws.nstack = 0;
+            if (nch == 1) load_chunk(0);
+            need_walk = false;
+            if constexpr (MIXED) wrapf = group_needs_wrap(per, g, gext, wave_max(act ? Hw : 0.0));
+        }
+        if (!LISTED && need_walk) {
             sink_bounds(act, xi, Hw, sk);
             walk_reset(stack, ws, linear, g);
             walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
@@ -1110,8 +1147,12 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
         const GroupFilter fil = group_filter(act, xi, gc, H, per, g, gext);
         int qb = 0, qn = 0;   // candidate queue: first entry, entries
         bool first_chunk = true;
+        int chunk = 0;
         while (true) {
-            if (!first_chunk || !list_complete) {
+            if (LISTED && !list_complete) {
+                load_chunk(chunk);
+                ++chunk;
+            } else if (!LISTED && (!first_chunk || !list_complete)) {
                 if (!first_chunk) {
                     ws.ncand = 0;
                     walk<false>(g, per, slop, a.nodes, sk, stack, cand, ws);
@@ -1264,7 +1305,7 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
               if (t >= nload && qn == 0) break;
             }
             first_chunk = false;
-            if (ws.nstack == 0) break;  // walk finished
+            if (LISTED ? (list_complete || chunk == nch) : ws.nstack == 0) break;  // list finished
         }
         ++scans;
         // ---- Halley update per lane, safeguarded by a bracket (Sec. 2.3.3:
@@ -1327,7 +1368,11 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
         }
         if (__all(done)) break;
         if (scans >= a.maxit) break;
-        if (__any(want_walk)) { need_walk = true; ++rewalks; }
+        if (__any(want_walk)) {
+            if constexpr (LISTED) { defer_group(); return; }
+            need_walk = true;
+            ++rewalks;
+        }
     }
     // status word: the iteration limit reached, a non-finite result
     const bool iterlim = act && !done;
@@ -1361,16 +1406,22 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
     }
 }
 
-// One workgroup (one wave) per sink group, or (PERSIST) a resident grid
-// taking groups from the per-XCD queues.
-template <int K, bool MIXED, bool PERSIST>
+// Sweep kernel launch modes: a walking kernel (one workgroup per sink group,
+// each walking the tree itself), a listed one (the lists from k_walk), and a
+// listed one on a persistent grid taking groups from the per-XCD queues.
+// The listed kernels hold no walk code, which frees registers: at 2M, mixed
+// density spills 47 values instead of 152 and the mixed force kernel none
+// instead of 21.
+constexpr int kLmWalk = 0, kLmListed = 1, kLmPersistent = 2;
+
+template <int K, bool MIXED, int LM>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5 : 4))) void k_density(SweepArgs a) {
-    if constexpr (PERSIST) {
+    if constexpr (LM == kLmPersistent) {
         int k = 0;
         for (int64_t grp; (grp = next_group(a.queue, a.ngroups, k)) >= 0;)
-            density_group<K, MIXED>(a, grp);
+            density_group<K, MIXED, true>(a, grp);
     } else {
-        density_group<K, MIXED>(a, xcd_group(blockIdx.x, gridDim.x));
+        density_group<K, MIXED, LM == kLmListed>(a, xcd_group(blockIdx.x, gridDim.x));
     }
 }
 
@@ -1382,55 +1433,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // distance tests, the fourth wave of the mixed kernel (128 VGPRs, 52 of its
 // values spilled to scratch) cost more than it hid (2M mixed forces 3.81 ms
 // at four waves, 3.24 at three).
-// The force pass's walk and refinement of each sink group, as a kernel of its
-// own before the force kernel: each step of the walk waits on memory, and at
-// this kernel's occupancy (84 VGPRs, five waves per SIMD, against the force
-// kernel's three) the waits of more groups overlap.  The refined candidate
-// buckets and the walk state go to global memory; the walk stack stays where
-// it is, so a group whose list does not fit continues the walk in the force
-// kernel.  The same code and inputs as the force kernel's own walk, hence
-// the same list.
-__global__ __launch_bounds__(kWave) void k_walk_force(SweepArgs a) {
-    __shared__ uint32_t cand[kCandCap];
-    __shared__ alignas(16) float stage[kRefineStageBytes / 4];
-    const int lane = threadIdx.x;
-    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
-    uint32_t *const stack = a.wstack + grp * kStackCap;
-    const int sid = a.grp_set[grp];
-    SetGeom g = a.sets[sid];
-    const bool per = a.periodic != 0;
-    const double slop = set_slop(g);
-    int64_t i;
-    bool act;
-    if (!group_sinks(a, g, grp, i, act)) return;
-    int level;
-    (void)group_bucket(a, g, i, act, level);
-    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
-    const double Hd = act ? a.Hs[i] : 0.0;
-    double gc[3];
-    for (int q = 0; q < 3; ++q) {
-        double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
-        gc[q] = 0.5 * (mn + mx);
-    }
-    double gext[3];
-    for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
-    const double Hsink_max = wave_max(act ? Hd : 0.0);
-    Sink sk;
-    sink_bounds(act, xi, Hd, sk);
-    WalkState ws{0, 0, -1, a.stack_limit, false, false};
-    walk_reset(stack, ws, false, g);
-    walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
-    if (!ws.overflow)
-        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
-    for (int t = lane; t < ws.ncand; t += kWave) a.glist[grp * kCandCap + t] = cand[t];
-    if (lane == 0) {
-        int32_t *w = a.gws + grp * kWalkWords;
-        w[0] = ws.nstack; w[1] = ws.ncand; w[2] = ws.lin; w[3] = ws.cap;
-        w[4] = ws.overflow ? 1 : 0; w[5] = ws.far ? 1 : 0;
-    }
-}
-
-template <int K, bool MIXED, bool RUNGS>
+template <int K, bool MIXED, bool RUNGS, bool LISTED>
 __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
@@ -1477,6 +1480,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     int64_t i;
     bool act;
     if (!group_sinks(a, g, grp, i, act)) return;
+    if (!LISTED && a.defer && a.defer[grp] == 0) return;
     int level;
     const int Bg = group_bucket(a, g, i, act, level);   // this group's bucket size
     const int lb = 31 - __builtin_clz((unsigned)Bg);     // Bg = 2^lb
@@ -1553,22 +1557,38 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     int retests = 0;   // pairs the wave re-tested in FP64
     unsigned long long cand_tested = 0;
     unsigned long long slots = 0;   // candidate slots loaded (before the filter)
-    // the first part of the list (and the stack, where the walk continues)
-    // comes from k_walk_force when it ran, already refined
-    bool pre = a.glist != nullptr, refined = pre;
-    if (!pre) walk_reset(stack, ws, linear, g);
+    // LISTED: the refined list comes from k_walk in chunks; a list too long
+    // to store leaves the group to the walking kernel
+    const int32_t *const hdr = LISTED ? a.whdr + grp * kWalkWords : nullptr;
+    int nch = 0, farm = 0, chunk = 0;
+    if constexpr (LISTED) {
+        const int flags = hdr[6];
+        if (flags & kListLong) {
+            if (lane == 0) {
+                a.defer[grp] = 1;
+                atomicAdd(&ctr[C_WALKED], 1ull);
+            }
+            return;
+        }
+        if (lane == 0) a.defer[grp] = 0;
+        if (flags & kListLinear) overflows = 1;
+        nch = hdr[0];
+        farm = hdr[5];
+    } else {
+        walk_reset(stack, ws, linear, g);
+    }
 
     while (true) {
-        if (pre) {
-            pre = false;
-            const int32_t *w = a.gws + grp * kWalkWords;
-            ws.nstack = w[0]; ws.ncand = w[1]; ws.lin = w[2]; ws.cap = w[3];
-            ws.overflow = w[4] != 0; ws.far = w[5] != 0;
-            for (int t = lane; t < ws.ncand; t += kWave) cand[t] = a.glist[grp * kCandCap + t];
-            __syncthreads();
-        } else {
-            walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
-        }
+      if constexpr (LISTED) {
+        if (chunk == nch) break;
+        ws.ncand = hdr[1 + chunk];
+        ws.far = ((farm >> chunk) & 1) != 0;
+        const uint32_t *src = a.wlist + grp * kListCap + chunk * kCandCap;
+        for (int t = lane; t < ws.ncand; t += kWave) cand[t] = src[t];
+        __syncthreads();
+        ++chunk;
+      } else {
+        walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
         if (ws.overflow) {
             // restart the whole pass with the linear bucket test
             ++overflows;
@@ -1580,13 +1600,11 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
             cand_tested = 0;
             slots = 0;
             amu[lane] = 0;
-            refined = false;
             walk_reset(stack, ws, true, g);
             continue;
         }
-        if (!refined)
-            refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
-        refined = false;
+        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
+      }
         const int nload = sweep_tiles(ws.ncand, Bg);
         int qb = 0, qn = 0;   // candidate queue: first entry, entries
         // One tile: the 64 queue entries from qb (nv of them valid).
@@ -1795,8 +1813,10 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
           }
           if (t >= nload && qn == 0) break;
         }
-        if (ws.nstack == 0) break;
-        ws.ncand = 0;
+        if constexpr (!LISTED) {
+            if (ws.nstack == 0) break;
+            ws.ncand = 0;
+        }
     }
     __syncthreads();
     const R mumax = bits_to_real(amu[lane]);
@@ -1852,14 +1872,94 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     }
 }
 
-template <int K, bool MIXED, bool RUNGS, bool PERSIST>
+template <int K, bool MIXED, bool RUNGS, int LM>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_forces(SweepArgs a) {
-    if constexpr (PERSIST) {
+    if constexpr (LM == kLmPersistent) {
         int k = 0;
         for (int64_t grp; (grp = next_group(a.queue, a.ngroups, k)) >= 0;)
-            forces_group<K, MIXED, RUNGS>(a, grp);
+            forces_group<K, MIXED, RUNGS, true>(a, grp);
     } else {
-        forces_group<K, MIXED, RUNGS>(a, xcd_group(blockIdx.x, gridDim.x));
+        forces_group<K, MIXED, RUNGS, LM == kLmListed>(a, xcd_group(blockIdx.x, gridDim.x));
+    }
+}
+
+// The interaction list of each sink group for one sweep, as a kernel of its
+// own before the sweep: the walk (gather test at the search radius Hw of the
+// density pass, or the gather-or-scatter test at H of the force pass) and the
+// per-sink refinement, chunk after chunk, with the same code and inputs as
+// the walking sweep kernels use, hence the same chunks.  Each step of the
+// walk waits on memory; here (84 VGPRs, five waves per SIMD) the waits of
+// more groups overlap than in the sweep kernels, and those then hold no walk
+// code.  A list of more than kListChunks chunks is marked long and left to
+// the walking kernel.
+template <bool SCATTER>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5))) void k_walk(SweepArgs a) {
+    __shared__ uint32_t cand[kCandCap];
+    __shared__ alignas(16) float stage[kRefineStageBytes / 4];
+    const int lane = threadIdx.x;
+    const int64_t grp = xcd_group(blockIdx.x, gridDim.x);
+    uint32_t *const stack = a.wstack + grp * kStackCap;
+    const int sid = a.grp_set[grp];
+    SetGeom g = a.sets[sid];
+    const bool per = a.periodic != 0;
+    const double slop = set_slop(g);
+    int64_t i;
+    bool act;
+    if (!group_sinks(a, g, grp, i, act)) return;
+    int level;
+    (void)group_bucket(a, g, i, act, level);
+    const double xi[3] = {act ? a.xs[i] : 0.0, act ? a.ys[i] : 0.0, act ? a.zs[i] : 0.0};
+    // the radius the sweep walks with (density: its first search radius)
+    double Rw;
+    if constexpr (SCATTER) {
+        Rw = act ? a.Hs[i] : 0.0;
+    } else {
+        const double cap = set_hcap(g, per, a.h_max);
+        double H = act ? a.Hs[i] : 0.0;
+        if (!(H > 0.0)) H = 0.01 * cap;
+        if (H > cap) H = cap;
+        Rw = fmin(a.oversel * H, cap);
+    }
+    double gc[3];
+    for (int q = 0; q < 3; ++q) {
+        double mn = wave_min(act ? xi[q] : DBL_MAX), mx = wave_max(act ? xi[q] : -DBL_MAX);
+        gc[q] = 0.5 * (mn + mx);
+    }
+    double gext[3];
+    for (int q = 0; q < 3; ++q) gext[q] = wave_max(act ? fabs(xi[q] - gc[q]) : 0.0);
+    const double Rmax = wave_max(act ? Rw : 0.0);
+    Sink sk;
+    sink_bounds(act, xi, Rw, sk);
+    WalkState ws{0, 0, -1, a.stack_limit, false, false};
+    walk_reset(stack, ws, false, g);
+    uint32_t *const out = a.wlist_out + grp * kListCap;
+    int32_t *const h = a.whdr_out + grp * kWalkWords;
+    int nch = 0, farm = 0, flags = 0;
+    while (true) {
+        walk<SCATTER>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        if (ws.overflow) {
+            // the stack was too small: the whole list again as the linear test
+            flags |= kListLinear;
+            nch = 0;
+            farm = 0;
+            walk_reset(stack, ws, true, g);
+            continue;
+        }
+        refine<SCATTER>(g, per, slop, a.nodes, xi, Rw, Rmax, act, gc, gext, cand, stage, ws);
+        if (ws.ncand > 0) {
+            if (nch == kListChunks) { flags |= kListLong; break; }
+            for (int t = lane; t < ws.ncand; t += kWave) out[nch * kCandCap + t] = cand[t];
+            if (lane == 0) h[1 + nch] = ws.ncand;
+            farm |= (ws.far ? 1 : 0) << nch;
+            ++nch;
+        }
+        if (ws.nstack == 0) break;
+        ws.ncand = 0;
+    }
+    if (lane == 0) {
+        h[0] = nch;
+        h[5] = farm;
+        h[6] = flags;
     }
 }
 
@@ -2296,35 +2396,65 @@ unsigned persistent_grid(Ctx *c, F kernel, int &cache) {
     return (unsigned)(c->ngroups < cap ? c->ngroups : cap);
 }
 
+// The launches of one sweep.  With stored lists (a context that holds the
+// buffers; not in the substeps of individual time steps) the listed sweep
+// kernel, one workgroup per group or persistent, then the walking kernel for
+// the groups the listed one left (the others return at once); else the
+// walking kernel for every group.
 template <int K, bool MIXED>
 void launch_density_k(Ctx *c, SweepArgs &a, hipStream_t s) {
+    const unsigned ng = (unsigned)c->ngroups;
+    if (!a.defer) {
+        k_density<K, MIXED, kLmWalk><<<ng, kWave, 0, s>>>(a);
+        return;
+    }
     if (a.queue) {
         static int occ = 0;
-        const unsigned grid = persistent_grid(c, k_density<K, MIXED, true>, occ);
-        k_density<K, MIXED, true><<<grid, kWave, 0, s>>>(a);
+        const unsigned grid = persistent_grid(c, k_density<K, MIXED, kLmPersistent>, occ);
+        k_density<K, MIXED, kLmPersistent><<<grid, kWave, 0, s>>>(a);
     } else {
-        k_density<K, MIXED, false><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+        k_density<K, MIXED, kLmListed><<<ng, kWave, 0, s>>>(a);
     }
+    k_density<K, MIXED, kLmWalk><<<ng, kWave, 0, s>>>(a);
 }
 
 template <int K, bool MIXED>
 void launch_forces_k(Ctx *c, SweepArgs &a, hipStream_t s) {
+    const unsigned ng = (unsigned)c->ngroups;
+    c->sweep_workgroups = c->ngroups;
+    c->sweep_launch = SPH_LAUNCH_GROUPS;
     if (a.rpack) {
-        // (individual time steps: one workgroup per group of the sink list)
-        c->sweep_workgroups = c->ngroups;
-        c->sweep_launch = SPH_LAUNCH_GROUPS;
-        k_forces<K, MIXED, true, false><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
-    } else if (a.queue) {
+        // (individual time steps: one walking workgroup per group of the sink list)
+        c->sweep_launch = SPH_LAUNCH_WALK;
+        k_forces<K, MIXED, true, kLmWalk><<<ng, kWave, 0, s>>>(a);
+        return;
+    }
+    if (!a.defer) {
+        c->sweep_launch = SPH_LAUNCH_WALK;
+        k_forces<K, MIXED, false, kLmWalk><<<ng, kWave, 0, s>>>(a);
+        return;
+    }
+    if (a.queue) {
         static int occ = 0;
-        const unsigned grid = persistent_grid(c, k_forces<K, MIXED, false, true>, occ);
+        const unsigned grid = persistent_grid(c, k_forces<K, MIXED, false, kLmPersistent>, occ);
         c->sweep_workgroups = grid;
         c->sweep_launch = SPH_LAUNCH_PERSISTENT;
-        k_forces<K, MIXED, false, true><<<grid, kWave, 0, s>>>(a);
+        k_forces<K, MIXED, false, kLmPersistent><<<grid, kWave, 0, s>>>(a);
     } else {
-        c->sweep_workgroups = c->ngroups;
-        c->sweep_launch = SPH_LAUNCH_GROUPS;
-        k_forces<K, MIXED, false, false><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+        k_forces<K, MIXED, false, kLmListed><<<ng, kWave, 0, s>>>(a);
     }
+    k_forces<K, MIXED, false, kLmWalk><<<ng, kWave, 0, s>>>(a);
+}
+
+// With stored lists: the walk kernel of the sweep writes them (and the
+// sweep's launches read them).
+template <bool SCATTER>
+hipError_t launch_walk(Ctx *c, SweepArgs &a, hipStream_t s) {
+    a.wlist = a.wlist_out = c->d_wlist;
+    a.whdr = a.whdr_out = c->d_whdr;
+    a.defer = c->d_defer;
+    k_walk<SCATTER><<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 // The launch shape of the context: a persistent launch clears its queue
@@ -2368,6 +2498,11 @@ hipError_t launch_density(Ctx *c, hipStream_t s) {
     SweepArgs a = base_args(c);
     hipError_t e = set_launch(c, a, c->sweep_sinks != nullptr, s);
     if (e != hipSuccess) return e;
+    if (c->d_wlist && c->launch != SPH_LAUNCH_WALK && !c->sweep_sinks) {
+        mark(c, E_DWALK0, s);
+        e = launch_walk<false>(c, a, s);
+        if (e != hipSuccess) return e;
+    }
     mark(c, E_DEN0, s);
     e = c->prm.precision == SPH_PREC_MIXED ? density_dispatch<true>(c, a, s)
                                            : density_dispatch<false>(c, a, s);
@@ -2397,12 +2532,9 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
     a.entropy = (c->prm.flags & SPH_FLAG_ENTROPY) ? 1 : 0;
     hipError_t e = set_launch(c, a, a.rpack != nullptr, s);
     if (e != hipSuccess) return e;
-    if (c->d_glist) {
-        a.glist = c->d_glist;
-        a.gws = c->d_gws;
+    if (c->d_wlist && c->launch != SPH_LAUNCH_WALK && !a.rpack) {
         mark(c, E_FWALK0, s);
-        k_walk_force<<<(unsigned)c->ngroups, kWave, 0, s>>>(a);
-        e = hipGetLastError();
+        e = launch_walk<true>(c, a, s);
         if (e != hipSuccess) return e;
     }
     mark(c, E_FOR0, s);

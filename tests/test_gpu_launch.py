@@ -1,13 +1,17 @@
 """Launch shapes of the sweeps on the GPU, through the C interface.
 
-A persistent launch (as many workgroups as the GPU holds at once, taking sink
-groups from per-XCD queues) runs the same per-group code as the launch of one
-workgroup per sink group; only which workgroup runs a group differs.  Every
-result must therefore equal the per-group launch's bit for bit, and every
-counter exactly: single sets (clouds, clumped with dynamic bucket sizing, the
-interface correction, the entropy update and the evolved density), a batch of
-uneven sets, a replayed HIP graph (the queue counters are cleared inside the
-graph), fewer groups than resident workgroups, and the autotuner's choice.
+Three shapes run the same per-group arithmetic: sweep kernels that walk the
+tree themselves (one workgroup per sink group), and sweep kernels that read
+each group's interaction list from a walk kernel run before them, either one
+workgroup per group or a persistent grid taking groups from per-XCD queues.
+Lists too long to store, and density groups whose root lies beyond the stored
+list, go back to the walking kernel.  Every result must equal the walking
+shape's bit for bit, and every counter exactly: single sets (clouds, clumped
+with dynamic bucket sizing, the interface correction, the entropy update and
+the evolved density), a batch of uneven sets, a replayed HIP graph (the
+queue counters are cleared inside the graph), fewer groups than resident
+workgroups, groups sent back to the walking kernel, and the autotuner's
+choice.
 """
 import numpy as np
 import pytest
@@ -92,18 +96,22 @@ def test_persistent_equals_per_group(sph, case, precision):
     name, state, p, offs = case
     p = dict(p, precision=precision)
     print(f"launch shapes {name} {precision} n={len(state['x'])}", flush=True)
-    a, sa = run(sph, state, p, offs, "groups")
-    b, sb = run(sph, state, p, offs, "persistent")
-    for k in FIELDS:
-        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
-    for k, (x, y) in enumerate(zip(sa, sb)):
-        assert x["launch"] == sph.LAUNCH_GROUPS and y["launch"] == sph.LAUNCH_PERSISTENT
-        for c in COUNTERS:
-            assert x[c] == y[c], (k, c)
-    # the resident grid: at most one workgroup per sink group
+    w, sw = run(sph, state, p, offs, "walk")
     ngroups = sum((n + 63) // 64 for n in np.diff(offs)) if offs else (len(state["x"]) + 63) // 64
-    assert sa[-1]["workgroups_force"] == ngroups
-    assert 1 <= sb[-1]["workgroups_force"] <= ngroups
+    for shape, code in (("groups", sph.LAUNCH_GROUPS), ("persistent", sph.LAUNCH_PERSISTENT)):
+        b, sb = run(sph, state, p, offs, shape)
+        for k in FIELDS:
+            np.testing.assert_array_equal(w[k], b[k], err_msg=f"{shape} {k}")
+        for k, (x, y) in enumerate(zip(sw, sb)):
+            assert x["launch"] == sph.LAUNCH_WALK and y["launch"] == code
+            for c in COUNTERS:
+                assert x[c] == y[c], (shape, k, c)
+        # the resident grid: at most one workgroup per sink group
+        if shape == "persistent":
+            assert 1 <= sb[-1]["workgroups_force"] <= ngroups
+        else:
+            assert sb[-1]["workgroups_force"] == ngroups
+    assert sw[-1]["workgroups_force"] == ngroups
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -142,11 +150,9 @@ def test_autotune_chooses_a_shape(sph):
     print(f"autotune: bucket {b}, launch {st['launch']}, workgroups {st['workgroups_force']}",
           flush=True)
     assert b in (8, 16, 32, 64)
-    assert st["launch"] in (sph.LAUNCH_GROUPS, sph.LAUNCH_PERSISTENT)
+    assert st["launch"] in (sph.LAUNCH_GROUPS, sph.LAUNCH_PERSISTENT, sph.LAUNCH_WALK)
     # the state it leaves is sph_init's with the chosen shape
-    c2 = sph.Context(dict(c["params"], bucket=b,
-                          launch="persistent" if st["launch"] == sph.LAUNCH_PERSISTENT
-                          else "groups"))
+    c2 = sph.Context(dict(c["params"], bucket=b, launch=int(st["launch"])))
     c2.init(ref)
     got, want = P.numpy(), ref.numpy()
     for k in ("H", "rho", "ax", "dudt", "dt"):
@@ -156,6 +162,34 @@ def test_autotune_chooses_a_shape(sph):
 def test_launch_parameter_checked(sph):
     c = si.uniform_box(28, 8, "m4", 32)
     with pytest.raises(sph.SphError):
-        sph.Context(dict(c["params"], launch=2))
+        sph.Context(dict(c["params"], launch=3))
     with pytest.raises(sph.SphError):
         sph.Context(dict(c["params"], launch="persistent", rungs=True, rung_max=4))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("guess", [0.25, 0.3], ids=["long-lists", "root-beyond-list"])
+def test_groups_sent_back_to_the_walking_kernel(sph, precision, guess):
+    """A first guess of H far from the root: at 0.25 (the cap) the density
+    pass's stored lists would exceed 1024 buckets of 8, so every group goes
+    back to the walking kernel; at 0.3 of the converged H the root lies beyond
+    the stored list's radius, and the group leaves the listed kernel when its
+    iteration wants a new walk.  Either way the results equal the walking
+    shape's bit for bit."""
+    c = si.random_cloud(31, 60000, kernel="wc4", n_ngb=100, periodic=True)
+    s, p = dict(c["state"]), dict(c["params"], precision=precision, bucket=8)
+    if guess == 0.3:
+        s["H"] = 0.3 * s["H"]
+    else:
+        s["H"] = np.full_like(s["H"], guess)
+    print(f"groups sent back: {precision}, H guess {guess}", flush=True)
+    w, sw = run(sph, s, p, None, "walk", steps=1)
+    b, sb = run(sph, s, p, None, "groups", steps=1)
+    for k in FIELDS:
+        np.testing.assert_array_equal(w[k], b[k], err_msg=k)
+    for c_ in COUNTERS:
+        assert sw[0][c_] == sb[0][c_], c_
+    print(f"  init: {sb[0]['groups_walked']} of {(60000 + 63) // 64} groups walked again, "
+          f"{sb[0]['n_rewalk']} new walks", flush=True)
+    assert sb[0]["groups_walked"] > 0
+    assert sw[0]["groups_walked"] == 0
