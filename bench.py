@@ -131,7 +131,7 @@ def run_gpu(case, precision, steps, warmup, graph=False):
     bucket = p.get("bucket", 32)
     if case.get("autotune"):
         bucket = ctx.autotune(P)
-    tden, tfor, ttree, ttot, twalk = [], [], [], [], []
+    tden, tfor, ttree, ttot, twalk, tdwalk = [], [], [], [], [], []
     for w in range(warmup):
         if graph and w >= warmup - 3:
             # the replayed graph runs the same kernels: their durations are
@@ -142,7 +142,7 @@ def run_gpu(case, precision, steps, warmup, graph=False):
             st = ctx.stats()
             tden.append(st["t_density_ms"]); tfor.append(st["t_forces_ms"])
             ttree.append(st["t_tree_ms"]); ttot.append(st["t_total_ms"])
-            twalk.append(st["t_force_walk_ms"])
+            twalk.append(st["t_force_walk_ms"]); tdwalk.append(st["t_density_walk_ms"])
     ctx.set_timing(False)
     torch.cuda.synchronize()
     if graph:
@@ -167,7 +167,7 @@ def run_gpu(case, precision, steps, warmup, graph=False):
             st = ctx.stats()
             tden.append(st["t_density_ms"]); tfor.append(st["t_forces_ms"])
             ttree.append(st["t_tree_ms"]); ttot.append(st["t_total_ms"])
-            twalk.append(st["t_force_walk_ms"])
+            twalk.append(st["t_force_walk_ms"]); tdwalk.append(st["t_density_walk_ms"])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         ctx.set_timing(False)
@@ -192,10 +192,12 @@ def run_gpu(case, precision, steps, warmup, graph=False):
     if tden:
         res.update({"t_density_ms": float(np.mean(tden)), "t_forces_ms": float(np.mean(tfor)),
                     "t_tree_ms": float(np.mean(ttree)), "t_step_ms": float(np.mean(ttot)),
-                    "t_force_walk_ms": float(np.mean(twalk))})
-        # (the sweeps: density, the force pass's walk kernel and the force kernel)
+                    "t_force_walk_ms": float(np.mean(twalk)),
+                    "t_density_walk_ms": float(np.mean(tdwalk))})
+        # (the sweeps: the walk kernels and the density and force kernels)
         res["metric_rate"] = (st["pairs_density"] + st["pairs_force"]) / \
-            (1e-3 * (res["t_density_ms"] + max(res["t_force_walk_ms"], 0.0) + res["t_forces_ms"]))
+            (1e-3 * (max(res["t_density_walk_ms"], 0.0) + res["t_density_ms"] +
+                     max(res["t_force_walk_ms"], 0.0) + res["t_forces_ms"]))
     ctx.close()
     del P
     torch.cuda.empty_cache()
@@ -449,8 +451,8 @@ def main():
         "mixed_vs_fp64": (results["mixed"]["pairs_per_s"] / results["fp64"]["pairs_per_s"])
         if "mixed" in results and "fp64" in results else None,
         "metric_rate_density_force_only": head.get("metric_rate"),
-        "phases_ms": {k: head.get(k) for k in ("t_tree_ms", "t_density_ms", "t_force_walk_ms",
-                                               "t_forces_ms", "t_step_ms")},
+        "phases_ms": {k: head.get(k) for k in ("t_tree_ms", "t_density_walk_ms", "t_density_ms",
+                                               "t_force_walk_ms", "t_forces_ms", "t_step_ms")},
         "pairs": {k: head[k] for k in ("pairs_density", "pairs_force", "cand_density",
                                        "cand_force", "nr_scans_mean", "n_overflow",
                                        "slots_density", "slots_force", "groups_by_level")},
