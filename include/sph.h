@@ -349,12 +349,13 @@ sph_status sph_graph_capture_step(sph_ctx *ctx, sph_particles *p, double dt, voi
 sph_status sph_graph_launch(sph_ctx *ctx, void *stream);
 
 /* Picks the bucket size (8, 16, 32, 64) and the sweeps' launch shape
- * (SPH_LAUNCH_*; one workgroup per group only with SPH_FLAG_RUNGS) by timing
- * the density and force passes of sph_init for every combination on the given
- * particles, each from the same first guess of H (synchronises; leaves H, rho,
- * omega, P, c, a, dudt, dt written as by sph_init).  The choice is kept in the
- * context; returns the bucket size in *bucket and the launch shape in
- * sph_stats.launch. */
+ * (SPH_LAUNCH_*; SPH_LAUNCH_GROUPS only with SPH_FLAG_RUNGS) for the given
+ * particles.  Every combination runs sph_init from the same first guess of H,
+ * then a density and a force pass from the converged H.  Those two passes are
+ * timed, walk kernels included; with SPH_FLAG_RUNGS, sph_init's own passes
+ * are.  Synchronises.  Leaves H, rho, omega, P, c, a, dudt, dt as sph_init
+ * writes them.  The choice is kept in the context; the bucket size comes
+ * back in *bucket and the launch shape in sph_stats.launch. */
 sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *stream);
 
 /* Turns device-side phase timing on (1) or off (0); timings appear in sph_stats.

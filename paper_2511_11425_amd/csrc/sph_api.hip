@@ -1058,10 +1058,26 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
             e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
             if (e != hipSuccess) break;
             st = sph_init(ctx, p, n, stream);
+            // timed: a density and a force pass from the converged H, as in a
+            // step (sph_init's own density pass starts from the first guess),
+            // each with its walk kernel (smaller buckets shorten the sweeps'
+            // lists but lengthen the walks)
             sph_stats ss;
-            if (st == SPH_OK) st = sph_get_stats(ctx, &ss);
-            if (st == SPH_OK && ss.t_density_ms >= 0 && ss.t_forces_ms >= 0)
-                t = std::min(t, ss.t_density_ms + ss.t_forces_ms);
+            double td = -1.0, tf = -1.0;
+            if (c.rungs_on) {
+                if (st == SPH_OK) st = sph_get_stats(ctx, &ss);
+                if (st == SPH_OK) { td = ss.t_density_ms; tf = ss.t_forces_ms; }
+            } else {
+                if (st == SPH_OK) st = sph_density(ctx, p, stream);
+                if (st == SPH_OK) st = sph_get_stats(ctx, &ss);
+                if (st == SPH_OK && ss.t_density_ms >= 0)
+                    td = ss.t_density_ms + std::max(ss.t_density_walk_ms, 0.0);
+                if (st == SPH_OK) st = sph_forces(ctx, p, stream);
+                if (st == SPH_OK) st = sph_get_stats(ctx, &ss);
+                if (st == SPH_OK && ss.t_forces_ms >= 0)
+                    tf = ss.t_forces_ms + std::max(ss.t_force_walk_ms, 0.0);
+            }
+            if (td >= 0 && tf >= 0) t = std::min(t, td + tf);
         }
         if (t < tbest) { tbest = t; best = cands[q % 4]; best_launch = c.launch; }
     }
