@@ -188,6 +188,7 @@ def run_gpu(case, precision, steps, warmup, graph=False):
         "launch": {sph.LAUNCH_GROUPS: "groups", sph.LAUNCH_PERSISTENT: "persistent",
                    sph.LAUNCH_WALK: "walk"}[st["launch"]],
         "workgroups_force": st["workgroups_force"],
+        "groups_walked": st["groups_walked"],
     }
     if tden:
         res.update({"t_density_ms": float(np.mean(tden)), "t_forces_ms": float(np.mean(tfor)),
@@ -455,7 +456,8 @@ def main():
                                                "t_force_walk_ms", "t_forces_ms", "t_step_ms")},
         "pairs": {k: head[k] for k in ("pairs_density", "pairs_force", "cand_density",
                                        "cand_force", "nr_scans_mean", "n_overflow",
-                                       "slots_density", "slots_force", "groups_by_level")},
+                                       "slots_density", "slots_force", "groups_by_level",
+                                       "groups_walked")},
         "roofline": roof,
         "errors_vs_oracle": errs or None,
         "cpu_baseline": cpu,
