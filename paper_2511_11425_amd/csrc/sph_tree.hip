@@ -424,26 +424,35 @@ __device__ inline void ball_union(const double *c1, double r1, const double *c2,
     *r = R * (1.0 + 1e-12) + 1e-12 * (fabs(c[0]) + fabs(c[1]) + fabs(c[2]));
 }
 
-// Node t of height d (t counts the nodes of that height over all sets, in set
-// order) from its two children.
-__device__ __forceinline__ void combine_one(const SetGeom *__restrict__ sets, int nsets,
-                                            const int64_t *__restrict__ pref, int64_t t, int d,
-                                            Node *__restrict__ nodes) {
-    int lo = 0, hi = nsets - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (pref[mid] <= t) lo = mid; else hi = mid - 1;
-    }
-    const SetGeom &g = sets[lo];
-    int64_t h = (int64_t)(g.nbp >> d) + (t - pref[lo]);
-    const Node a = nodes[g.node0 + 2 * h];
-    const Node b = nodes[g.node0 + 2 * h + 1];
-    Node o;
+// A node's bounds from its two children's.
+__device__ __forceinline__ void combine_nodes(const Node &a, const Node &b, Node &o) {
     for (int q = 0; q < 3; ++q) {
         o.clo[q] = fmin(a.clo[q], b.clo[q]); o.chi[q] = fmax(a.chi[q], b.chi[q]);
         o.blo[q] = fmin(a.blo[q], b.blo[q]); o.bhi[q] = fmax(a.bhi[q], b.bhi[q]);
     }
     ball_union(a.bc, a.br, b.bc, b.br, o.bc, &o.br);
+}
+
+// The set holding node t of a height whose per-set node counts have the
+// prefix pref (t counts the nodes of that height over all sets, in set order).
+__device__ __forceinline__ int set_of_node(const int64_t *__restrict__ pref, int nsets, int64_t t) {
+    int lo = 0, hi = nsets - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Node t of height d from its two children.
+__device__ __forceinline__ void combine_one(const SetGeom *__restrict__ sets, int nsets,
+                                            const int64_t *__restrict__ pref, int64_t t, int d,
+                                            Node *__restrict__ nodes) {
+    const int lo = set_of_node(pref, nsets, t);
+    const SetGeom &g = sets[lo];
+    int64_t h = (int64_t)(g.nbp >> d) + (t - pref[lo]);
+    Node o;
+    combine_nodes(nodes[g.node0 + 2 * h], nodes[g.node0 + 2 * h + 1], o);
     nodes[g.node0 + h] = o;
 }
 
@@ -454,19 +463,38 @@ __global__ void k_combine(const SetGeom *__restrict__ sets, int nsets,
     if (t < total) combine_one(sets, nsets, pref, t, d, nodes);
 }
 
-// The small top heights d0..d1 in one workgroup, height after height (each
-// height reads what the one below wrote; the barrier orders them), instead of
-// one launch per height.
-constexpr int kTopThreads = 1024;
+// The small top heights d0..d1 (at most kTopThreads nodes each) in one
+// workgroup, one thread per node, height after height, instead of one launch
+// per height.  Each height's nodes stay in LDS (in the order of t) for the
+// next one, so only height d0 reads its children from global memory (a round
+// trip per height otherwise: 36 us for the eleven top heights at 2M).
+constexpr int kTopThreads = 512;
 __global__ __launch_bounds__(kTopThreads) void k_combine_top(const SetGeom *__restrict__ sets,
                                                              int nsets,
                                                              const int64_t *__restrict__ pref_all,
                                                              int d0, int d1, Node *__restrict__ nodes) {
+    __shared__ Node lv[kTopThreads];   // 64 KiB
+    const int64_t t = threadIdx.x;
     for (int d = d0; d <= d1; ++d) {
         const int64_t *pref = pref_all + (int64_t)d * (nsets + 1);
-        const int64_t total = pref[nsets];
-        for (int64_t t = threadIdx.x; t < total; t += kTopThreads)
-            combine_one(sets, nsets, pref, t, d, nodes);
+        const bool have = t < pref[nsets];
+        Node o;
+        if (have) {
+            const int lo = set_of_node(pref, nsets, t);
+            const SetGeom &g = sets[lo];
+            const int64_t j = t - pref[lo];
+            const int64_t h = (int64_t)(g.nbp >> d) + j;
+            if (d == d0) {
+                combine_nodes(nodes[g.node0 + 2 * h], nodes[g.node0 + 2 * h + 1], o);
+            } else {
+                // the children: nodes 2j and 2j + 1 of this set at height d - 1
+                const int64_t c = pref_all[(int64_t)(d - 1) * (nsets + 1) + lo] + 2 * j;
+                combine_nodes(lv[c], lv[c + 1], o);
+            }
+            nodes[g.node0 + h] = o;
+        }
+        __syncthreads();   // (every read of height d - 1 is done)
+        if (have) lv[t] = o;
         __syncthreads();
     }
 }
