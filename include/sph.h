@@ -166,7 +166,7 @@ typedef struct {
                           dt_max 2^-rung_max).  Default 8. */
     int32_t launch;    /* launch shape of the density and force sweeps.  The first two
                           take each sink group's interaction list from a walk kernel
-                          run before the sweep (stored in the context, up to 1024
+                          run before the sweep (stored in the context, up to 4096
                           buckets per group; a longer list, or in the density pass a
                           root beyond the stored list's radius, sends the group to a
                           sweep kernel that walks the tree itself):

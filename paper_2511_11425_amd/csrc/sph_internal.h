@@ -57,11 +57,12 @@ constexpr int kXcds = 8;
 constexpr int kQueueStride = 64;   // uint32 per queue counter
 // Stored interaction lists (the walk kernels): up to kListChunks chunks of at
 // most kCandCap refined buckets per sink group, and a header of kWalkWords:
-// chunks, the bucket count of each chunk, the chunks' minimum-image flags (a
-// bit each), and kList* flags
-constexpr int kListChunks = 4;
+// [0] chunks, [1] the chunks' minimum-image flags (a bit each), [2] kList*
+// flags, [3 + c] the bucket count of chunk c
+constexpr int kListChunks = 16;
 constexpr int kListCap = kListChunks * kCandCap;
-constexpr int kWalkWords = 8;
+constexpr int kWalkWords = 3 + kListChunks;
+static_assert(kListChunks <= 32, "minimum-image flags: one bit per chunk");
 constexpr int kListLong = 1;       // more than kListChunks chunks: not stored
 constexpr int kListLinear = 2;     // the walk outgrew its stack and ran as the linear test
 static_assert(C_NCOUNTERS <= kCntStride, "counter copy too small");

@@ -1085,7 +1085,7 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
     const int32_t *const hdr = LISTED ? a.whdr + grp * kWalkWords : nullptr;
     int nch = 0, farm = 0;
     auto load_chunk = [&](int c) {
-        ws.ncand = hdr[1 + c];
+        ws.ncand = hdr[3 + c];
         ws.far = ((farm >> c) & 1) != 0;
         const uint32_t *src = a.wlist + grp * kListCap + c * kCandCap;
         for (int t = lane; t < ws.ncand; t += kWave) cand[t] = src[t];
@@ -1100,12 +1100,12 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
 
     while (true) {
         if (need_walk && LISTED) {
-            const int flags = hdr[6];
+            const int flags = hdr[2];
             if (flags & kListLong) { defer_group(); return; }
             if (lane == 0) a.defer[grp] = 0;
             if (flags & kListLinear) ++overflows;
             nch = hdr[0];
-            farm = hdr[5];
+            farm = hdr[1];
             list_complete = nch <= 1;
             ws.ncand = 0;
             ws.nstack = 0;
@@ -1562,7 +1562,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     const int32_t *const hdr = LISTED ? a.whdr + grp * kWalkWords : nullptr;
     int nch = 0, farm = 0, chunk = 0;
     if constexpr (LISTED) {
-        const int flags = hdr[6];
+        const int flags = hdr[2];
         if (flags & kListLong) {
             if (lane == 0) {
                 a.defer[grp] = 1;
@@ -1573,7 +1573,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
         if (lane == 0) a.defer[grp] = 0;
         if (flags & kListLinear) overflows = 1;
         nch = hdr[0];
-        farm = hdr[5];
+        farm = hdr[1];
     } else {
         walk_reset(stack, ws, linear, g);
     }
@@ -1581,7 +1581,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     while (true) {
       if constexpr (LISTED) {
         if (chunk == nch) break;
-        ws.ncand = hdr[1 + chunk];
+        ws.ncand = hdr[3 + chunk];
         ws.far = ((farm >> chunk) & 1) != 0;
         const uint32_t *src = a.wlist + grp * kListCap + chunk * kCandCap;
         for (int t = lane; t < ws.ncand; t += kWave) cand[t] = src[t];
@@ -1949,7 +1949,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5))) void
         if (ws.ncand > 0) {
             if (nch == kListChunks) { flags |= kListLong; break; }
             for (int t = lane; t < ws.ncand; t += kWave) out[nch * kCandCap + t] = cand[t];
-            if (lane == 0) h[1 + nch] = ws.ncand;
+            if (lane == 0) h[3 + nch] = ws.ncand;
             farm |= (ws.far ? 1 : 0) << nch;
             ++nch;
         }
@@ -1958,8 +1958,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5))) void
     }
     if (lane == 0) {
         h[0] = nch;
-        h[5] = farm;
-        h[6] = flags;
+        h[1] = farm;
+        h[2] = flags;
     }
 }
 

@@ -168,16 +168,16 @@ def test_launch_parameter_checked(sph):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("guess", [0.25, 0.3], ids=["long-lists", "root-beyond-list"])
+@pytest.mark.parametrize("guess", [0.5, 0.3], ids=["long-lists", "root-beyond-list"])
 def test_groups_sent_back_to_the_walking_kernel(sph, precision, guess):
-    """A first guess of H far from the root: at 0.25 (the cap) the density
-    pass's stored lists would exceed 1024 buckets of 8, so every group goes
-    back to the walking kernel; at 0.3 of the converged H the root lies beyond
-    the stored list's radius, and the group leaves the listed kernel when its
-    iteration wants a new walk.  Either way the results equal the walking
-    shape's bit for bit."""
+    """A first guess of H far from the root: at 0.5 (the cap with h_max 0.5)
+    the density pass's stored lists would exceed 4096 buckets of 8, so the
+    groups go back to the walking kernel; at 0.3 of the converged H the root
+    lies beyond the stored list's radius, and the group leaves the listed
+    kernel when its iteration wants a new walk.  Either way the results equal
+    the walking shape's bit for bit."""
     c = si.random_cloud(31, 60000, kernel="wc4", n_ngb=100, periodic=True)
-    s, p = dict(c["state"]), dict(c["params"], precision=precision, bucket=8)
+    s, p = dict(c["state"]), dict(c["params"], precision=precision, bucket=8, h_max=0.5)
     if guess == 0.3:
         s["H"] = 0.3 * s["H"]
     else:
