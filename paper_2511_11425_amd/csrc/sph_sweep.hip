@@ -985,26 +985,30 @@ __device__ __forceinline__ bool needs_image(bool per, const SetGeom &g, const do
 // (one per sink group, as for the force kernels), leaving 6-7 KiB of LDS; the
 // mixed kernel is held to 96 VGPRs, five waves per SIMD, the FP64 one to 128,
 // four waves.  The values that then spill to scratch cost less than the
-// latency the extra waves hide (measured at 2M: mixed 2.48 ms at three
-// waves, 2.21 at four, 2.13 at five; FP64 7.29 at three, 6.83 at four).
+// latency the extra waves hide (measured at 2M with the walk inside: mixed
+// 2.48 ms at three waves, 2.21 at four, 2.13 at five; FP64 7.29 at three,
+// 6.83 at four; with stored lists: mixed 1.48 ms at five waves, 1.59 at
+// four; FP64 5.24 at four, 5.59 at three).
 template <int K, bool MIXED, bool LISTED>
 __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     __shared__ uint32_t cand[kCandCap];
     __shared__ uint16_t ring[kRing];
     // candidate queue (x y z m, a ring of kQueue entries; tiles are its
-    // halves) and, in the mixed path, the candidates' sorted indices,
-    // per-sink counts of pairs the FP64 re-test rejected and the sinks' FP64
-    // H (exact membership); while the walk refines its list the same LDS
-    // holds the refinement stage
-    constexpr int kTileBytes = 4 * kQueue * (int)sizeof(R) + (MIXED ? kQueue * 4 + kWave * 12 : 0);
+    // halves) and, in the mixed path, the candidates' squared offsets from
+    // the group centre and sorted indices, per-sink counts of pairs the FP64
+    // re-test rejected and the sinks' FP64 H (exact membership); while the
+    // walk refines its list the same LDS holds the refinement stage
+    constexpr int kTileBytes =
+        4 * kQueue * (int)sizeof(R) + (MIXED ? kQueue * 8 + kWave * 12 : 0);
     __shared__ alignas(16) unsigned char tile_buf[kTileBytes > kRefineStageBytes ? kTileBytes
                                                                                   : kRefineStageBytes];
     R *const qx_ = reinterpret_cast<R *>(tile_buf);
     R *const qy_ = qx_ + kQueue;
     R *const qz_ = qy_ + kQueue;
     R *const qm_ = qz_ + kQueue;
-    int32_t *const qj_ = reinterpret_cast<int32_t *>(qm_ + kQueue);
+    R *const qc_ = qm_ + kQueue;   // (mixed)
+    int32_t *const qj_ = reinterpret_cast<int32_t *>(qm_ + (MIXED ? 2 : 1) * kQueue);
     int32_t *const srej = qj_ + kQueue;
     double *const sH = reinterpret_cast<double *>(srej + kWave);
     float *const stage = reinterpret_cast<float *>(tile_buf);
@@ -1142,6 +1146,24 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
             MIXED ? guard_band(gmax, wave_min(act ? H : DBL_MAX), wrapf ? Lmax : 0.0) : 0.0;
         const R H2 = MIXED ? (R)(H * H * (1.0 + band)) : (R)(H * H);
         const R qlo = (R)(1.0 - band);
+        // mixed, tiles without re-wrapping: the distance test in expanded
+        // form, |A|^2 - 2 A.B < H2' - |B|^2 for candidate A and sink B (both
+        // offsets from the group centre), three FMAs per candidate.  Its
+        // rounding error stays below u (6 |A|^2 + 6 |A||B| + 4 |B|^2) + u H2'
+        // (u = 2^-24), with |B| <= sqrt(3) G and, for a pair the difference
+        // form r^2 < H2 accepts, |A| <= |B| + 1.01 H; H2' = H2 (1 + loose),
+        // loose twice that bound over H^2 plus the difference form's own
+        // 4.2 u, so it accepts every pair the difference form accepts.  The
+        // few it accepts beyond lie past the band and go to the FP64 re-test,
+        // which rejects them: the sets stay exact.
+        R m2qx = R(0), m2qy = R(0), m2qz = R(0), TsX = R(0);
+        if constexpr (MIXED) {
+            const double S = 1.7320508075688772 * gmax / (act ? H : 1.0);
+            const double A_ = S + 1.01;
+            const double loose = 0x1p-23 * (6.0 * A_ * A_ + 6.0 * A_ * S + 4.0 * S * S + 8.0);
+            m2qx = -2.0f * qx; m2qy = -2.0f * qy; m2qz = -2.0f * qz;
+            TsX = (R)((double)H2 * (1.0 + loose)) - fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+        }
         sp[lane].w = Hinv;
         // the group's bounds at this scan's H (candidate filter)
         const GroupFilter fil = group_filter(act, xi, gc, H, per, g, gext);
@@ -1181,10 +1203,11 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
             // One tile: the 64 queue entries from qb (nv of them valid).
             auto run_tile = [&](int nv) {
                 R *const tx = qx_ + qb, *const ty = qy_ + qb, *const tz = qz_ + qb,
-                         *const tm = qm_ + qb;
+                         *const tm = qm_ + qb, *const tc = qc_ + qb;
                 const int32_t *const tj = qj_ + qb;
                 if (lane >= nv) {
                     tx[lane] = (R)NAN; ty[lane] = R(0); tz[lane] = R(0); tm[lane] = R(0);
+                    if constexpr (MIXED) tc[lane] = (R)NAN;
                 }
                 if constexpr (!MIXED)
                     wrapf = __any(lane < nv && needs_image(per, g, gc, gext, (double)tx[lane],
@@ -1204,10 +1227,21 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
                         for (int h = 0; h < 8; h += 4) {
                             const V4<R> X = ld4(tx + k0 + h), Y = ld4(ty + k0 + h),
                                         Z = ld4(tz + k0 + h);
-                            b = push_hit(b, r2of(X.x, Y.x, Z.x), H2);
-                            b = push_hit(b, r2of(X.y, Y.y, Z.y), H2);
-                            b = push_hit(b, r2of(X.z, Y.z, Z.z), H2);
-                            b = push_hit(b, r2of(X.w, Y.w, Z.w), H2);
+                            if constexpr (MIXED && !WRAP) {
+                                const V4<R> C = ld4(tc + k0 + h);
+                                auto ex = [&](R x, R y, R z, R c) -> R {
+                                    return fmaf(x, m2qx, fmaf(y, m2qy, fmaf(z, m2qz, c)));
+                                };
+                                b = push_hit(b, ex(X.x, Y.x, Z.x, C.x), TsX);
+                                b = push_hit(b, ex(X.y, Y.y, Z.y, C.y), TsX);
+                                b = push_hit(b, ex(X.z, Y.z, Z.z, C.z), TsX);
+                                b = push_hit(b, ex(X.w, Y.w, Z.w, C.w), TsX);
+                            } else {
+                                b = push_hit(b, r2of(X.x, Y.x, Z.x), H2);
+                                b = push_hit(b, r2of(X.y, Y.y, Z.y), H2);
+                                b = push_hit(b, r2of(X.z, Y.z, Z.z), H2);
+                                b = push_hit(b, r2of(X.w, Y.w, Z.w), H2);
+                            }
                         }
                         return b;
                     }, [&](int s, int k) {
@@ -1292,7 +1326,10 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)kb, 0u))) &
                                    (kQueue - 1);
                     qx_[at] = px; qy_[at] = py; qz_[at] = pz; qm_[at] = pm;
-                    if constexpr (MIXED) qj_[at] = (int32_t)j;
+                    if constexpr (MIXED) {
+                        qj_[at] = (int32_t)j;
+                        qc_[at] = fmaf(px, px, fmaf(py, py, pz * pz));
+                    }
                 }
                 qn += __popcll(kb);
               }
@@ -1432,7 +1469,9 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // SIMD with up to 168 VGPRs: once the candidate filter had halved the
 // distance tests, the fourth wave of the mixed kernel (128 VGPRs, 52 of its
 // values spilled to scratch) cost more than it hid (2M mixed forces 3.81 ms
-// at four waves, 3.24 at three).
+// at four waves, 3.24 at three).  Without the walk code (stored lists) the
+// mixed kernel needs 135 VGPRs and spills nothing at three waves; at four it
+// spills 5 and measured 3.07 ms against 2.90.
 template <int K, bool MIXED, bool RUNGS, bool LISTED>
 __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;

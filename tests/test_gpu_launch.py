@@ -184,12 +184,13 @@ def test_groups_sent_back_to_the_walking_kernel(sph, precision, guess):
         s["H"] = np.full_like(s["H"], guess)
     print(f"groups sent back: {precision}, H guess {guess}", flush=True)
     w, sw = run(sph, s, p, None, "walk", steps=1)
-    b, sb = run(sph, s, p, None, "groups", steps=1)
-    for k in FIELDS:
-        np.testing.assert_array_equal(w[k], b[k], err_msg=k)
-    for c_ in COUNTERS:
-        assert sw[0][c_] == sb[0][c_], c_
-    print(f"  init: {sb[0]['groups_walked']} of {(60000 + 63) // 64} groups walked again, "
-          f"{sb[0]['n_rewalk']} new walks", flush=True)
-    assert sb[0]["groups_walked"] > 0
     assert sw[0]["groups_walked"] == 0
+    for shape in ("groups", "persistent"):
+        b, sb = run(sph, s, p, None, shape, steps=1)
+        for k in FIELDS:
+            np.testing.assert_array_equal(w[k], b[k], err_msg=f"{shape} {k}")
+        for c_ in COUNTERS:
+            assert sw[0][c_] == sb[0][c_], (shape, c_)
+        print(f"  {shape} init: {sb[0]['groups_walked']} of {(60000 + 63) // 64} groups walked "
+              f"again, {sb[0]['n_rewalk']} new walks", flush=True)
+        assert sb[0]["groups_walked"] > 0
