@@ -1306,7 +1306,9 @@ __device__ __forceinline__ void density_group(const SweepArgs &a, const int64_t 
                 bool keep = false;
                 if (j >= 0) {
                     double d0 = cur.x - gc[0], d1 = cur.y - gc[1], d2 = cur.z - gc[2];
-                    if (per) {
+                    // (no kept bucket of this chunk reaches near half a box
+                    // from gc unless ws.far: the image is then the identity)
+                    if (per && ws.far) {
                         d0 = min_image(d0, g.L[0], g.halfL[0]);
                         d1 = min_image(d1, g.L[1], g.halfL[1]);
                         d2 = min_image(d2, g.L[2], g.halfL[2]);
@@ -1817,7 +1819,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
             bool keep = false;
             if (j >= 0) {
                 double d0 = cur.x - gc[0], d1 = cur.y - gc[1], d2 = cur.z - gc[2];
-                if (per) {
+                if (per && ws.far) {   // (see the density pass)
                     d0 = min_image(d0, g.L[0], g.halfL[0]);
                     d1 = min_image(d1, g.L[1], g.halfL[1]);
                     d2 = min_image(d2, g.L[2], g.halfL[2]);
