@@ -1477,7 +1477,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 template <int K, bool MIXED, bool RUNGS, bool LISTED>
 __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
-    __shared__ uint32_t cand[kCandCap];
+    // (the listed FP64 kernel reads its chunk of the stored list in place:
+    // the kilobyte of LDS it saves lets it, whose LDS limits its occupancy,
+    // hold eleven workgroups per CU instead of ten; FP64 forces at 2M 5.07 ->
+    // 4.86 ms.  The mixed kernel, limited by its registers, copies the chunk
+    // to LDS: read in place it took 2.93 ms against 2.87.)
+    __shared__ uint32_t cand_lds[(LISTED && !MIXED) ? 1 : kCandCap];
+    const uint32_t *cand_rd = cand_lds;
     __shared__ uint16_t ring[kRing];
     // candidate queue (a ring of kQueue entries; tiles are its halves): what
     // the distance test reads, x y z and H^2, and the sorted index through
@@ -1625,11 +1631,15 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
         ws.ncand = hdr[3 + chunk];
         ws.far = ((farm >> chunk) & 1) != 0;
         const uint32_t *src = a.wlist + grp * kListCap + chunk * kCandCap;
-        for (int t = lane; t < ws.ncand; t += kWave) cand[t] = src[t];
-        __syncthreads();
+        if constexpr (MIXED) {
+            for (int t = lane; t < ws.ncand; t += kWave) cand_lds[t] = src[t];
+            __syncthreads();
+        } else {
+            cand_rd = src;
+        }
         ++chunk;
       } else {
-        walk<true>(g, per, slop, a.nodes, sk, stack, cand, ws);
+        walk<true>(g, per, slop, a.nodes, sk, stack, cand_lds, ws);
         if (ws.overflow) {
             // restart the whole pass with the linear bucket test
             ++overflows;
@@ -1644,7 +1654,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
             walk_reset(stack, ws, true, g);
             continue;
         }
-        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand, stage, ws);
+        refine<true>(g, per, slop, a.nodes, xi, Hd, Hsink_max, act, gc, gext, cand_lds, stage, ws);
       }
         const int nload = sweep_tiles(ws.ncand, Bg);
         int qb = 0, qn = 0;   // candidate queue: first entry, entries
@@ -1802,8 +1812,9 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
         // itself, before the walk refines again, whose stage shares this LDS).
         // the next load's slot is fetched while this one is filtered
         auto load_slot = [&](int t) -> Slot {
-            const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cand, ws.ncand, t, nload, lb)
-                                                 : slot_index(g, cand, ws.ncand, t << (6 - lb), Bg);
+            const uint32_t *const cl = (LISTED && !MIXED) ? cand_rd : cand_lds;
+            const int64_t j = (MIXED || !ws.far) ? sweep_slot(g, cl, ws.ncand, t, nload, lb)
+                                                 : slot_index(g, cl, ws.ncand, t << (6 - lb), Bg);
             if (j < 0) return Slot{-1, 0.0, 0.0, 0.0, 0.0};
             return Slot{j, a.xs[j], a.ys[j], a.zs[j], a.Hs[j]};
         };
