@@ -178,9 +178,9 @@ typedef struct {
                           SPH_LAUNCH_WALK: one workgroup per sink group, each walking the
                             tree itself (no stored lists).
                           Results do not depend on it, only the cost; sph_autotune picks
-                          one.  SPH_FLAG_RUNGS takes SPH_LAUNCH_GROUPS only, and its
-                          substeps walk in the sweep kernels; sph_init_noalloc walks in the
-                          sweep kernels.  Default SPH_LAUNCH_GROUPS. */
+                          one.  SPH_FLAG_RUNGS takes SPH_LAUNCH_GROUPS only, and such a
+                          context (like sph_init_noalloc) walks in the sweep kernels.
+                          Default SPH_LAUNCH_GROUPS. */
     double fastgas;    /* SPH_FLAG_RUNGS: active fraction below which the density pass is
                           restricted (0 = never).  Default 0. */
 } sph_params;
