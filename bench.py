@@ -411,8 +411,11 @@ def main():
         kidx = KERNEL_INDEX[case["params"].get("kernel", "m4")]
         # (kernel template: ..., launch mode 0 walking, 1 listed, 2 listed persistent)
         lm = {"walk": 0, "groups": 1, "persistent": 2}[head["launch"]]
+        # (forces: no rung maximum; the fifth accumulator unless FP64 without the
+        # evolved density in a listed shape)
+        ev = "true" if (mixed or lm == 0 or "evolved" in case.get("schemes", [])) else "false"
         kname = f"k_{dom}<{kidx}, {'true' if mixed else 'false'}" + \
-            (f", false, {lm}>" if dom == "forces" else f", {lm}>")   # (forces: no rung maximum)
+            (f", false, {lm}, {ev}>" if dom == "forces" else f", {lm}>")
         achieved = flops / t
         roof = {"bound": "alu", "kernel": kname, "achieved": achieved / 1e12,
                 "peak": PEAK[dtype] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[dtype],

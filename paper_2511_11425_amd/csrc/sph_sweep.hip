@@ -1474,7 +1474,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(MIXED ? 5
 // at four waves, 3.24 at three).  Without the walk code (stored lists) the
 // mixed kernel needs 135 VGPRs and spills nothing at three waves; at four it
 // spills 5 and measured 3.07 ms against 2.90.
-template <int K, bool MIXED, bool RUNGS, bool LISTED>
+// EV: room for the evolved density's continuity sum (a fifth per-sink
+// accumulator).  Without it the FP64 kernel's LDS admits twelve workgroups
+// per CU instead of eleven (2M FP64 forces 4.85 -> 4.72 ms).
+template <int K, bool MIXED, bool RUNGS, bool LISTED, bool EV>
 __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t grp) {
     typedef typename std::conditional<MIXED, float, double>::type R;
     // (the listed FP64 kernel reads its chunk of the stored list in place:
@@ -1511,7 +1514,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     __shared__ R trm[MIXED ? kWave : 1];
     __shared__ V4<R> sp[kWave], sv[kWave], sq[kWave];  // sink: (x H) (v 1/H) (A c rho sigma/H^5)
     typedef typename std::conditional<MIXED, uint32_t, unsigned long long>::type Bits;
-    __shared__ double acc[5][kWave];   // a_x a_y a_z du/dt, sum m (v_ij . x_ij) G_i
+    __shared__ double acc[EV ? 5 : 4][kWave];   // a_x a_y a_z du/dt, sum m (v_ij . x_ij) G_i
     __shared__ Bits amu[kWave];   // bits of max(0, -mu) (non-negative, so integer order)
     // individual time steps: largest rung over F_i, sorted index of each sink,
     // pairs whose neighbour's density is not of this substep (FastGas)
@@ -1581,7 +1584,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
                      (R)(act ? a.vzs[i] : 0.0), act ? R(1) / Hi : R(0)};
     const double hinv_i = act ? 1.0 / Hd : 0.0, h2_i = hinv_i * hinv_i;
     sq[lane] = V4<R>{Ai, ci, (R)(act ? a.rhos[i] : 1.0), (R)(sigma_of<K>() * h2_i * h2_i * hinv_i)};
-    for (int q = 0; q < 5; ++q) acc[q][lane] = 0;
+    for (int q = 0; q < (EV ? 5 : 4); ++q) acc[q][lane] = 0;
     amu[lane] = 0;
     if constexpr (RUNGS) {
         armax[lane] = -1;
@@ -1772,7 +1775,9 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
                         // du/dt: A_i m_j G_i v.x + (1/2) m_j Pi Gbar v.x (A_i is the sink's)
                         atomicAdd(&acc[3][s],
                                   (double)(mj * vdotx * (pdv * iq.x * Gi + R(0.5) * Pi * Gbar)));
-                        if (evolved) atomicAdd(&acc[4][s], (double)(mj * vdotx * Gi));
+                        if constexpr (EV) {
+                            if (evolved) atomicAdd(&acc[EV ? 4 : 0][s], (double)(mj * vdotx * Gi));
+                        }
                         if (mu < R(0)) lds_max_nonneg(&amu[s], -mu);
                     }
                     if constexpr (RUNGS) {
@@ -1800,7 +1805,7 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
             if (wrapf) tile(std::true_type{});
             else tile(std::false_type{});
             __syncthreads();
-            for (int q = 0; q < (evolved ? 5 : 4); ++q) {
+            for (int q = 0; q < ((EV && evolved) ? 5 : 4); ++q) {
                 acc_d[q] += acc[q][lane];
                 acc[q][lane] = 0;
             }
@@ -1924,14 +1929,14 @@ __device__ __forceinline__ void forces_group(const SweepArgs &a, const int64_t g
     }
 }
 
-template <int K, bool MIXED, bool RUNGS, int LM>
+template <int K, bool MIXED, bool RUNGS, int LM, bool EV = true>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_forces(SweepArgs a) {
     if constexpr (LM == kLmPersistent) {
         int k = 0;
         for (int64_t grp; (grp = next_group(a.queue, a.ngroups, k)) >= 0;)
-            forces_group<K, MIXED, RUNGS, true>(a, grp);
+            forces_group<K, MIXED, RUNGS, true, EV>(a, grp);
     } else {
-        forces_group<K, MIXED, RUNGS, LM == kLmListed>(a, xcd_group(blockIdx.x, gridDim.x));
+        forces_group<K, MIXED, RUNGS, LM == kLmListed, EV>(a, xcd_group(blockIdx.x, gridDim.x));
     }
 }
 
@@ -2486,14 +2491,26 @@ void launch_forces_k(Ctx *c, SweepArgs &a, hipStream_t s) {
         k_forces<K, MIXED, false, kLmWalk><<<ng, kWave, 0, s>>>(a);
         return;
     }
-    if (a.queue) {
-        static int occ = 0;
-        const unsigned grid = persistent_grid(c, k_forces<K, MIXED, false, kLmPersistent>, occ);
-        c->sweep_workgroups = grid;
-        c->sweep_launch = SPH_LAUNCH_PERSISTENT;
-        k_forces<K, MIXED, false, kLmPersistent><<<grid, kWave, 0, s>>>(a);
+    // (the listed FP64 kernels without the evolved density take four
+    // accumulators; every other kernel five)
+    auto listed = [&](auto ev_tag) {
+        constexpr bool EV = decltype(ev_tag)::value;
+        if (a.queue) {
+            static int occ = 0;
+            const unsigned grid =
+                persistent_grid(c, k_forces<K, MIXED, false, kLmPersistent, EV>, occ);
+            c->sweep_workgroups = grid;
+            c->sweep_launch = SPH_LAUNCH_PERSISTENT;
+            k_forces<K, MIXED, false, kLmPersistent, EV><<<grid, kWave, 0, s>>>(a);
+        } else {
+            k_forces<K, MIXED, false, kLmListed, EV><<<ng, kWave, 0, s>>>(a);
+        }
+    };
+    if constexpr (MIXED) {
+        listed(std::true_type{});
     } else {
-        k_forces<K, MIXED, false, kLmListed><<<ng, kWave, 0, s>>>(a);
+        if (a.drho) listed(std::true_type{});
+        else listed(std::false_type{});
     }
     k_forces<K, MIXED, false, kLmWalk><<<ng, kWave, 0, s>>>(a);
 }
