@@ -68,6 +68,37 @@ constexpr int kListLinear = 2;     // the walk outgrew its stack and ran as the 
 static_assert(C_NCOUNTERS <= kCntStride, "counter copy too small");
 __host__ __device__ inline int64_t cnt_shard(int64_t g) { return (g % kCntShards) * kCntStride; }
 
+// A lane's value after a DPP move within its row of 16 lanes (CTRL: the DPP
+// control word: 0xB1 and 0x4E swap neighbours and pairs of a quad, 0x141
+// mirrors each half row, 0x140 the row).  The two halves of a double move
+// separately.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    // (a lane whose source is not valid keeps its own value, which leaves a
+    // minimum or maximum unchanged)
+    const int l0 = (int)(b & 0xffffffffll), h0 = (int)(b >> 32);
+    const int lo = __builtin_amdgcn_update_dpp(l0, l0, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(h0, h0, CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Minimum (MAX: maximum) over aligned segments of B lanes (B = 8, 16, 32 or
+// 64), left in every lane of the segment: within a quad by two swaps, then
+// each half row with its mirror (lane i meets lane 7 - i of the other quad),
+// each row with its mirror, then across rows by lane shuffles.
+template <bool MAX>
+__device__ __forceinline__ double seg_reduce(double v, int B) {
+    auto op = [](double a, double b) { return MAX ? fmax(a, b) : fmin(a, b); };
+    v = op(v, dpp_move<0xB1>(v));
+    v = op(v, dpp_move<0x4E>(v));
+    v = op(v, dpp_move<0x141>(v));
+    if (B >= 16) v = op(v, dpp_move<0x140>(v));
+    if (B >= 32) v = op(v, __shfl_xor(v, 16));
+    if (B >= 64) v = op(v, __shfl_xor(v, 32));
+    return v;
+}
+
 // Timing events recorded around the phases when timing is on.
 enum TimingEvent {
     E_BEGIN = 0, E_TREE0, E_TREE1, E_DWALK0, E_DEN0, E_DEN1, E_FWALK0, E_FOR0, E_FOR1, E_END,

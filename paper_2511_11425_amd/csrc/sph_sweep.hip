@@ -157,14 +157,8 @@ __device__ __forceinline__ double uniform(double v) {
     const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ __forceinline__ double wave_min(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return uniform(v);
-}
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return uniform(v);
-}
+__device__ __forceinline__ double wave_min(double v) { return uniform(seg_reduce<false>(v, 64)); }
+__device__ __forceinline__ double wave_max(double v) { return uniform(seg_reduce<true>(v, 64)); }
 __device__ __forceinline__ int wave_sum_i(int v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
