@@ -178,8 +178,9 @@ typedef struct {
                           SPH_LAUNCH_WALK: one workgroup per sink group, each walking the
                             tree itself (no stored lists).
                           Results do not depend on it, only the cost; sph_autotune picks
-                          one.  SPH_FLAG_RUNGS takes SPH_LAUNCH_GROUPS only, and such a
-                          context (like sph_init_noalloc) walks in the sweep kernels.
+                          one.  SPH_FLAG_RUNGS takes SPH_LAUNCH_GROUPS or SPH_LAUNCH_WALK
+                          (its substeps sweep the groups of the sink lists);
+                          sph_init_noalloc walks in the sweep kernels.
                           Default SPH_LAUNCH_GROUPS. */
     double fastgas;    /* SPH_FLAG_RUNGS: active fraction below which the density pass is
                           restricted (0 = never).  Default 0. */

@@ -119,7 +119,7 @@ bool valid_params(const sph_params *p, std::string &why) {
         why = "launch must be SPH_LAUNCH_GROUPS, SPH_LAUNCH_PERSISTENT or SPH_LAUNCH_WALK";
         return false;
     }
-    if ((p->flags & SPH_FLAG_RUNGS) && p->launch != SPH_LAUNCH_GROUPS) {
+    if ((p->flags & SPH_FLAG_RUNGS) && p->launch == SPH_LAUNCH_PERSISTENT) {
         why = "SPH_FLAG_RUNGS launches one workgroup per sink group"; return false;
     }
     if (p->flags & SPH_FLAG_RUNGS) {
@@ -300,11 +300,9 @@ sph_status setup(sph_ctx *x, int64_t n, hipStream_t s) {
         if (c.prm.fastgas > 0.0) A(c.mark, n + 2);
     }
     A(c.d_wstack, (size_t)std::max<int64_t>(c.ngroups, 1) * kStackCap);
-    if (!c.rungs_on) {
-        A(c.d_wlist, (size_t)std::max<int64_t>(c.ngroups, 1) * kListCap);
-        A(c.d_whdr, (size_t)std::max<int64_t>(c.ngroups, 1) * kWalkWords);
-        A(c.d_defer, (size_t)std::max<int64_t>(c.ngroups, 1));
-    }
+    A(c.d_wlist, (size_t)std::max<int64_t>(c.ngroups, 1) * kListCap);
+    A(c.d_whdr, (size_t)std::max<int64_t>(c.ngroups, 1) * kWalkWords);
+    A(c.d_defer, (size_t)std::max<int64_t>(c.ngroups, 1));
     A(c.d_queue, kXcds * kQueueStride);
     A(c.d_scan_tmp, c.scan_tmp_len);
     A(c.d_cnt, kCntShards * kCntStride);
@@ -1045,14 +1043,14 @@ sph_status sph_autotune(sph_ctx *ctx, sph_particles *p, int32_t *bucket, void *s
     double tbest = 1e300;
     // every bucket size with every launch shape (substeps of individual time
     // steps launch one walking workgroup per group only)
-    const int shapes[3] = {SPH_LAUNCH_GROUPS, SPH_LAUNCH_PERSISTENT, SPH_LAUNCH_WALK};
-    const int nlaunch = c.rungs_on ? 1 : 3;
+    const int shapes[3] = {SPH_LAUNCH_GROUPS, SPH_LAUNCH_WALK, SPH_LAUNCH_PERSISTENT};
+    const int nlaunch = c.rungs_on ? 2 : 3;
     for (int q = 0; q < 4 * nlaunch && st == SPH_OK && e == hipSuccess; ++q) {
         // (dynamic sizing: the tree keeps buckets of 8; the trials set the
         // level the groups start from)
         if (c.dyn) c.base_bucket = cands[q % 4];
         else c.bucket = cands[q % 4];
-        c.launch = c.rungs_on ? SPH_LAUNCH_GROUPS : shapes[q / 4];
+        c.launch = shapes[q / 4];
         double t = 1e300;
         for (int rep = 0; rep < 2 && st == SPH_OK && e == hipSuccess; ++rep) {
             e = hipMemcpyAsync(p->H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, s);

@@ -2475,8 +2475,14 @@ void launch_forces_k(Ctx *c, SweepArgs &a, hipStream_t s) {
     c->sweep_workgroups = c->ngroups;
     c->sweep_launch = SPH_LAUNCH_GROUPS;
     if (a.rpack) {
-        // (individual time steps: one walking workgroup per group of the sink list)
-        c->sweep_launch = SPH_LAUNCH_WALK;
+        // individual time steps: one workgroup per group of the sink list
+        // (with the rung maximum over F_i)
+        if (!a.defer) {
+            c->sweep_launch = SPH_LAUNCH_WALK;
+            k_forces<K, MIXED, true, kLmWalk><<<ng, kWave, 0, s>>>(a);
+            return;
+        }
+        k_forces<K, MIXED, true, kLmListed><<<ng, kWave, 0, s>>>(a);
         k_forces<K, MIXED, true, kLmWalk><<<ng, kWave, 0, s>>>(a);
         return;
     }
@@ -2561,7 +2567,7 @@ hipError_t launch_density(Ctx *c, hipStream_t s) {
     SweepArgs a = base_args(c);
     hipError_t e = set_launch(c, a, c->sweep_sinks != nullptr, s);
     if (e != hipSuccess) return e;
-    if (c->d_wlist && c->launch != SPH_LAUNCH_WALK && !c->sweep_sinks) {
+    if (c->d_wlist && c->launch != SPH_LAUNCH_WALK) {
         mark(c, E_DWALK0, s);
         e = launch_walk<false>(c, a, s);
         if (e != hipSuccess) return e;
@@ -2595,7 +2601,7 @@ hipError_t launch_forces(Ctx *c, hipStream_t s) {
     a.entropy = (c->prm.flags & SPH_FLAG_ENTROPY) ? 1 : 0;
     hipError_t e = set_launch(c, a, a.rpack != nullptr, s);
     if (e != hipSuccess) return e;
-    if (c->d_wlist && c->launch != SPH_LAUNCH_WALK && !a.rpack) {
+    if (c->d_wlist && c->launch != SPH_LAUNCH_WALK) {
         mark(c, E_FWALK0, s);
         e = launch_walk<true>(c, a, s);
         if (e != hipSuccess) return e;

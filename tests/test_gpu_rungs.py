@@ -162,7 +162,7 @@ def test_base_step_of_substeps_mixed(sph, orc, hot):
 def test_rung_combinations_rejected(sph, hot):
     st, p = hot
     for extra in ({"entropy": True}, {"interface": True}, {"dynamic": True},
-                  {"rung_max": 21}):
+                  {"rung_max": 21}, {"launch": "persistent"}):
         with pytest.raises(sph.SphError):
             sph.Context(dict(p, **extra))
     P = sph.ParticleArrays.from_state(st)
@@ -170,3 +170,30 @@ def test_rung_combinations_rejected(sph, hot):
     ctx.init(P)
     with pytest.raises(sph.SphError):
         ctx.step(P, dt=1e-3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_substeps_stored_lists_equal_walking(sph, hot, precision):
+    """The substeps with stored interaction lists (the default launch shape)
+    equal those of the sweep kernels that walk the tree themselves, bit for
+    bit, rungs, substep lengths and counters included."""
+    st, p = hot
+    out = {}
+    for shape in ("walk", "groups"):
+        P = sph.ParticleArrays.from_state(st)
+        ctx = sph.Context(dict(p, precision=precision, launch=shape))
+        print(f"substeps {precision} launch={shape}", flush=True)
+        ctx.init(P)
+        stats = []
+        for _ in range(12):
+            ctx.step(P)
+            s_ = ctx.stats()
+            stats.append((s_["t_units"], s_["n_active"], s_["dt_used"], s_["pairs_force"],
+                          s_["pairs_density"], s_["n_dens"]))
+        out[shape] = (P.numpy(), stats, ctx.stats()["launch"])
+        ctx.close()
+    (a, sa, la), (b, sb, lb) = out["walk"], out["groups"]
+    assert la == sph.LAUNCH_WALK and lb == sph.LAUNCH_GROUPS
+    assert sa == sb
+    for k in ("x", "vx", "u", "H", "rho", "omega", "ax", "dudt", "dt", "rung"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
